@@ -1,0 +1,166 @@
+/* mfq.h -- C ABI of the MI355X many-flavor quark-solve library (libmfq.so).
+ *
+ * The library computes, for N_f/2 independent pseudo-fermion fields
+ * Phi = (phi_1 .. phi_{N_f/2}) on one SU(3) gauge field U with Wilson quarks
+ * of hopping parameter kappa, the blocked quantities of the paper's Alg. 2:
+ *
+ *   X = D^-1 Phi,   Y = (D^+)^-1 X,   F_mu(n) = sum_i f[x_i, y_i]   (Eq. 3)
+ *
+ * and the pseudo-fermion action S_i = |D^-1 phi_i|^2 (Eq. 2).  The solves are
+ * conjugate gradients on the normal operator D^+ D run for all right-hand
+ * sides (RHS) at once, so that one link load serves every pseudo-fermion.
+ *
+ * Conventions (the paper writes none of them out; they are this library's):
+ *   (D psi)(n) = psi(n) - kappa sum_mu [ (1 - g_mu) U_mu(n) psi(n+mu)
+ *                                        + (1 + g_mu) U_mu(n-mu)^+ psi(n-mu) ],
+ *   chiral gamma basis g_mu = [[0, e_mu], [e_mu^+, 0]], e_0 = -1, e_k = -i sigma_k,
+ *   g_5 = diag(1, 1, -1, -1), mu = 0 is time, 1..3 are x, y, z.
+ *   Schroedinger-functional (SF) time boundaries: slices x0 = 0..T, spinors
+ *   vanish on x0 = 0 and x0 = T, so the dynamical slices are x0 = 1..T-1.
+ *
+ * Canonical boundary layouts (FP64, complex interleaved re/im, x fastest):
+ *   spinor  [n_rhs][t][z][y][x][spin 4][colour 3]   over the dynamical time
+ *           slices only (T-1 of them for SF, T otherwise);
+ *   links   [mu 4][x0][z][y][x][3][3]   over T+1 stored slices for SF (so the
+ *           fixed boundary links are representable), T otherwise;
+ *   force   same shape as the links: the Hermitian traceless matrix
+ *           G_mu(n) = sum_a F^a_mu(n) T^a, T^a = lambda^a/2, where
+ *           F^a = dS/dw^a under U_mu(n) -> exp(i w T^a) U_mu(n).  Links that
+ *           never enter D hold exactly 0.
+ *
+ * Ownership: every *_dev pointer is device memory owned by the caller (for
+ * example a torch tensor); the library never frees it.  The handle owns its
+ * packed copies of the links, its workspaces and solver state.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  mfq_dslash is
+ * asynchronous on it.  The solves and the force are host-blocking on return
+ * (convergence is data dependent and the statistics are host outputs); all
+ * their device work is ordered on `stream`.
+ *
+ * Errors: functions return an mfq_status.  Negative values are hard errors;
+ * mfq_last_error() then returns a message (thread local).  MFQ_NOT_CONVERGED
+ * still writes the best solution and per-RHS statistics.  Nothing aborts or
+ * throws across this boundary.  One handle must not be used by two threads at
+ * the same time.
+ */
+#ifndef MFQ_H
+#define MFQ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfq_handle mfq_handle;
+
+typedef enum {
+  MFQ_OK = 0,
+  MFQ_NOT_CONVERGED = 1, /* max_iter reached; best x and stats written       */
+  MFQ_FELL_BACK = 2,     /* learned preconditioner stagnated: CG finished it */
+  MFQ_ERR_ARG = -1,      /* invalid argument or non-finite input             */
+  MFQ_ERR_HIP = -2,      /* a HIP runtime call failed                        */
+  MFQ_ERR_NOMEM = -3,    /* device allocation failed                         */
+  MFQ_ERR_STATE = -4     /* call not valid in the handle's state             */
+} mfq_status;
+
+typedef enum { MFQ_BC_SF = 0, MFQ_BC_PERIODIC = 1, MFQ_BC_ANTIPERIODIC_T = 2 } mfq_bc;
+
+/* Precision of the inner CG iteration.  All forms keep the solution and the
+ * true residual in FP64 and reduce every dot product in FP64.
+ *   FP64            plain FP64 CG.
+ *   FP32_RELIABLE   FP32 vectors and links; FP64 reliable updates (the true
+ *                   residual b - A x is recomputed in FP64 whenever the inner
+ *                   residual has dropped by reliable_delta, and the FP32
+ *                   recursion continues from it).
+ *   FP16_REFINE     FP16 vectors (per-site FP32 norm) and FP16 links, FP32
+ *                   arithmetic, FP32 solution correction; FP64 defect
+ *                   correction (restart from the FP64 true residual).
+ * This is the mixed-precision (flexible) inner/outer split of Section 3.2,
+ * done on one GPU with the outer FP64 steps on the device. */
+typedef enum { MFQ_PREC_FP64 = 0, MFQ_PREC_FP32_RELIABLE = 1, MFQ_PREC_FP16_REFINE = 2 } mfq_prec;
+
+/* Operators for mfq_dslash (H is the hopping term, D = 1 - kappa H):
+ *   HOP_EO   out_even = H_eo in_odd,  out_odd = 0
+ *   HOP_OE   out_odd  = H_oe in_even, out_even = 0
+ *   HOP      out = H in     (both parities)      HOP_DAG  out = H^+ in
+ *   D, DDAG, DDAGD          out = D in, D^+ in, D^+ D in                   */
+typedef enum {
+  MFQ_OP_HOP_EO = 0,
+  MFQ_OP_HOP_OE = 1,
+  MFQ_OP_D = 2,
+  MFQ_OP_DDAG = 3,
+  MFQ_OP_DDAGD = 4,
+  MFQ_OP_HOP = 5,
+  MFQ_OP_HOP_DAG = 6
+} mfq_op;
+
+typedef enum { MFQ_PC_NONE = 0, MFQ_PC_PTC = 1 } mfq_pc;
+
+typedef struct {
+  int dims[4]; /* Lx, Ly, Lz, T: even, >= 2 (T >= 4 for SF)                  */
+  int bc;      /* mfq_bc                                                       */
+  double kappa;/* 0 < kappa < 0.25                                             */
+} mfq_lattice;
+
+typedef struct {
+  double tol;            /* per-RHS true relative residual |b - A x|/|b|     */
+  int max_iter;          /* inner iterations per RHS before NOT_CONVERGED    */
+  int prec;              /* mfq_prec                                          */
+  double reliable_delta; /* reliable-update trigger (<= 0: default 0.1)      */
+  int precond;           /* mfq_pc                                            */
+  int restart;           /* FGMRES restart length (PTC only; <= 0: 16)        */
+  int check_every;       /* iterations between host polls (<= 0: default)    */
+  int use_graph;         /* capture the inner iterations in a hipGraph        */
+} mfq_solve_params;
+
+typedef struct {
+  int iters;             /* inner iterations                                 */
+  int reliable_updates;  /* FP64 true-residual evaluations                   */
+  double true_rel_resid; /* final FP64 |b - A x| / |b|                        */
+  double seconds;        /* wall time of the whole call                      */
+  int status;            /* mfq_status of this RHS                            */
+} mfq_solve_stats;
+
+/* Create a handle for one lattice and pack the links (canonical FP64 device
+ * array, see above) into the internal FP64, FP32 and FP16 copies. */
+int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mfq_handle** out);
+
+/* Repack the links after they changed (for example after an MD step). */
+int mfq_update_links(mfq_handle* h, const double* links_dev, void* stream);
+
+/* out = op(in) for n_rhs canonical spinors, computed in FP64.  Asynchronous. */
+int mfq_dslash(mfq_handle* h, int op, const double* in_dev, double* out_dev, int n_rhs, void* stream);
+
+/* Same, with the storage/arithmetic precision of an inner solve (mfq_prec):
+ * the input is rounded to that precision, the operator applied in it, and the
+ * result widened back to FP64. */
+int mfq_dslash_prec(mfq_handle* h, int op, int prec, const double* in_dev, double* out_dev, int n_rhs,
+                    void* stream);
+
+/* x_i = (D^+ D)^-1 b_i for i < n_rhs, all RHS in one batched CG (Section 3.1:
+ * the blocked form of the linear equations).  stats_host: n_rhs records. */
+int mfq_solve_multi_rhs(mfq_handle* h, const double* b_dev, double* x_dev, int n_rhs,
+                        const mfq_solve_params* params, mfq_solve_stats* stats_host, void* stream);
+
+/* Alg. 2 for n_rhs pseudo-fermions: one batched normal-equation solve
+ * Z = (D^+ D)^-1 g5 Phi gives Y = (D^+)^-1 D^-1 Phi = g5 Z and X = D^-1 Phi =
+ * D^+ Y; then force_dev (links shape) = sum_i f[x_i, y_i] (Eq. 3) and
+ * action_host[i] = |x_i|^2 (Eq. 2).  x_dev / y_dev may be NULL; if given they
+ * receive X and Y (spinor shape). */
+int mfq_fermion_force(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq_solve_params* params,
+                      double* force_dev, double* action_host, double* x_dev, double* y_dev,
+                      mfq_solve_stats* stats_host, void* stream);
+
+/* Thread-local message for the last negative status. */
+const char* mfq_last_error(void);
+
+/* Average device time (ms) of one launch of the dominant solver kernel (the
+ * fused half-dslash of the inner CG at precision `prec` for n_rhs RHS), timed
+ * with HIP events around `iters` back-to-back launches on `stream`. */
+int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, double* ms_out);
+
+void mfq_destroy(mfq_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFQ_H */

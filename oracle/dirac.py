@@ -67,6 +67,10 @@ class WilsonDirac:
         if links.shape != want:
             raise ValueError(f"links shape {links.shape}, expected {want}")
         self.U = np.asarray(links, dtype=np.complex128)
+        # contiguous U^T and conj(U) so that the colour products below are
+        # plain batched matrix products
+        self._ut = np.ascontiguousarray(np.swapaxes(self.U, -1, -2))
+        self._uc = np.ascontiguousarray(self.U.conj())
 
     # ---- geometry -------------------------------------------------------
     def spinor_shape(self, n_rhs: int):
@@ -114,11 +118,11 @@ class WilsonDirac:
     # ---- colour products on full arrays -----------------------------------
     def u_times(self, mu: int, f: np.ndarray) -> np.ndarray:
         """(U_mu(n) f(n)) for every n; f is [rhs][x0][z][y][x][4][3]."""
-        return f @ np.swapaxes(self.U[mu], -1, -2)
+        return f @ self._ut[mu]
 
     def udag_times(self, mu: int, f: np.ndarray) -> np.ndarray:
         """(U_mu(n)^+ f(n)) for every n."""
-        return f @ self.U[mu].conj()
+        return f @ self._uc[mu]
 
     # ---- the operator -------------------------------------------------------
     def hop(self, psi: np.ndarray, dagger: bool = False) -> np.ndarray:

@@ -27,7 +27,9 @@ class CGStats:
 
 
 def _dot(a, b):
-    return np.vdot(a, b)
+    # elementwise product and sum (no threaded BLAS call: it contends with the
+    # OpenMP threads of the native operator)
+    return np.sum(a.conj() * b)
 
 
 def cg(apply_a, b: np.ndarray, tol: float, max_iter: int = 100000, x0=None):

@@ -1,0 +1,642 @@
+// C ABI of libmfq: handle management, argument validation, the batched
+// multi-RHS CG driver (FP64, FP32 with FP64 reliable updates, FP16 with FP64
+// defect correction), the blocked force of Alg. 2, and kernel timing.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+
+#include "internal.h"
+#include "mfq.h"
+
+using namespace mfq;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int fail_hip(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? MFQ_ERR_NOMEM : MFQ_ERR_HIP;
+}
+}  // namespace
+
+#define HIPCHK(...)                                          \
+  do {                                                       \
+    hipError_t e_ = (__VA_ARGS__);                           \
+    if (e_ != hipSuccess) return fail_hip(e_, #__VA_ARGS__); \
+  } while (0)
+
+namespace mfq {
+hipError_t ensure(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.ptr) return hipSuccess;
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+  if (bytes == 0) return hipSuccess;
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e == hipSuccess) b.bytes = bytes;
+  return e;
+}
+void release(DevBuf& b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+}  // namespace mfq
+
+struct Workspace {
+  OwnedField<double> b64, x64, r64, t64, y64;
+  OwnedField<double> xd, rd, pd, td;
+  OwnedField<float> xs, rs, ps, ts;
+  OwnedField<_Float16> rh, ph, th;
+  DevBuf part, sc, sums, bad;
+  int cap_part = 0;  // RHS capacity of the partial-sum slots
+  int nblk_max = 0;
+  CgScalars* host_sc = nullptr;
+  int host_cap = 0;
+};
+
+struct mfq_handle {
+  mfq_lattice lat;
+  Geom g;
+  int n_slices;
+  DevBuf links64, links32, links16;
+  Workspace ws;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+Links<double> links_d(mfq_handle* h) { return Links<double>{(const d2*)h->links64.ptr, h->g.vh}; }
+Links<float> links_f(mfq_handle* h) { return Links<float>{(const f2*)h->links32.ptr, h->g.vh}; }
+Links<_Float16> links_h(mfq_handle* h) { return Links<_Float16>{(const h2*)h->links16.ptr, h->g.vh}; }
+
+int check_lattice(const mfq_lattice* lat) {
+  if (!lat) return fail(MFQ_ERR_ARG, "lattice is NULL");
+  for (int d = 0; d < 4; ++d)
+    if (lat->dims[d] < 2 || lat->dims[d] % 2)
+      return fail(MFQ_ERR_ARG, "lattice dims must be even and >= 2");
+  if (lat->bc < MFQ_BC_SF || lat->bc > MFQ_BC_ANTIPERIODIC_T) return fail(MFQ_ERR_ARG, "unknown boundary condition");
+  if (lat->bc == MFQ_BC_SF && lat->dims[3] < 4) return fail(MFQ_ERR_ARG, "SF lattices need T >= 4");
+  if (!(lat->kappa > 0.0 && lat->kappa < 0.25)) return fail(MFQ_ERR_ARG, "kappa must be in (0, 0.25)");
+  const long vol = (long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+  if (vol > (1L << 28)) return fail(MFQ_ERR_ARG, "lattice volume too large");
+  return MFQ_OK;
+}
+
+int partials_ready(mfq_handle* h, int n_rhs) {
+  Workspace& w = h->ws;
+  const int nblk = (2 * h->g.vh + 63) / 64;
+  if (w.cap_part < n_rhs || w.nblk_max < nblk) {
+    HIPCHK(ensure(w.part, sizeof(double) * 4 * (size_t)n_rhs * nblk));
+    HIPCHK(ensure(w.sc, sizeof(CgScalars) * n_rhs));
+    HIPCHK(ensure(w.sums, sizeof(double) * n_rhs));
+    w.cap_part = n_rhs;
+    w.nblk_max = nblk;
+  }
+  HIPCHK(ensure(w.bad, sizeof(int)));
+  if (w.host_cap < n_rhs) {
+    if (w.host_sc) (void)hipHostFree(w.host_sc);
+    w.host_sc = nullptr;
+    HIPCHK(hipHostMalloc((void**)&w.host_sc, sizeof(CgScalars) * n_rhs, hipHostMallocDefault));
+    w.host_cap = n_rhs;
+  }
+  return MFQ_OK;
+}
+
+double* part_slot(mfq_handle* h, int slot) {
+  Workspace& w = h->ws;
+  return (double*)w.part.ptr + (size_t)slot * w.cap_part * w.nblk_max;
+}
+
+// Pack canonical spinors into b64 and verify they are finite (blocking).
+int pack_checked(mfq_handle* h, const double* canon, int n_rhs, int gamma5, hipStream_t st) {
+  Workspace& w = h->ws;
+  HIPCHK(hipMemsetAsync(w.bad.ptr, 0, sizeof(int), st));
+  HIPCHK(launch_pack_spinor<double>(h->g, canon, w.b64.view(h->g), n_rhs, gamma5, (int*)w.bad.ptr, st));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, w.bad.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return fail(MFQ_ERR_ARG, "input spinor holds NaN or Inf");
+  return MFQ_OK;
+}
+
+// ------------------------------------------------- operator application
+template <typename S, typename SX>
+HopArgs<S, SX> hop_args(mfq_handle* h, Links<S> L, int n_rhs) {
+  HopArgs<S, SX> a;
+  memset((void*)&a, 0, sizeof(a));
+  a.g = h->g;
+  a.links = L;
+  a.n_rhs = n_rhs;
+  a.skip_state = 3;
+  return a;
+}
+
+// out = op(in) in storage S; tmp is scratch (DDAGD only).  Fields are views.
+template <typename S>
+int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field<S> out, int n_rhs,
+             hipStream_t st) {
+  const Shape sh = default_shape(n_rhs);
+  const double mk = -h->lat.kappa;
+  HopArgs<S, S> a = hop_args<S, S>(h, L, n_rhs);
+  auto run = [&](int epi, Field<S> src, Field<S> dst, int par, int dag, double coef) -> hipError_t {
+    a.in = src;
+    a.self = src;
+    a.out = dst;
+    a.par = par;
+    a.dagger = dag;
+    a.coef = coef;
+    return launch_hop<S, S>(epi, a, sh, st);
+  };
+  switch (op) {
+    case MFQ_OP_HOP_EO:
+    case MFQ_OP_HOP_OE: {
+      const int par = op == MFQ_OP_HOP_EO ? 0 : 1;
+      // zero the other parity of the output, then the one hopping launch
+      const size_t per_par = (size_t)Store<S>::NC * h->g.vh;
+      for (int r = 0; r < n_rhs; ++r)
+        HIPCHK(hipMemsetAsync(out.data + ((size_t)r * 2 + (1 - par)) * per_par, 0,
+                              per_par * sizeof(typename Store<S>::chunk), st));
+      if (sizeof(S) == 2)
+        for (int r = 0; r < n_rhs; ++r)
+          HIPCHK(hipMemsetAsync(out.norm + ((size_t)r * 2 + (1 - par)) * h->g.vh, 0, h->g.vh * sizeof(float), st));
+      HIPCHK(run(EPI_HOP, in, out, par, 0, 1.0));
+      return MFQ_OK;
+    }
+    case MFQ_OP_HOP:
+    case MFQ_OP_HOP_DAG:
+      HIPCHK(run(EPI_HOP, in, out, 0, op == MFQ_OP_HOP_DAG, 1.0));
+      HIPCHK(run(EPI_HOP, in, out, 1, op == MFQ_OP_HOP_DAG, 1.0));
+      return MFQ_OK;
+    case MFQ_OP_D:
+    case MFQ_OP_DDAG:
+      HIPCHK(run(EPI_D, in, out, 0, op == MFQ_OP_DDAG, mk));
+      HIPCHK(run(EPI_D, in, out, 1, op == MFQ_OP_DDAG, mk));
+      return MFQ_OK;
+    case MFQ_OP_DDAGD:
+      HIPCHK(run(EPI_D, in, tmp, 0, 0, mk));
+      HIPCHK(run(EPI_D, in, tmp, 1, 0, mk));
+      HIPCHK(run(EPI_D, tmp, out, 0, 1, mk));
+      HIPCHK(run(EPI_D, tmp, out, 1, 1, mk));
+      return MFQ_OK;
+    default:
+      return fail(MFQ_ERR_ARG, "unknown operator");
+  }
+}
+
+// ------------------------------------------------------------- CG driver
+template <typename S, typename SX>
+struct InnerFields {
+  Links<S> L;
+  Field<S> r, p, t;
+  Field<SX> x;
+};
+
+struct Stat {
+  int status;
+};
+
+// Batched CG on D^+D for n RHS, b in ws.b64, solution in ws.x64.
+// The inner recursion runs in storage S; the solution correction in SX.  Every
+// RHS has its own scalars; converged RHS are masked out of the vector work.
+template <typename S, typename SX>
+int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> in, int set_p_on_update,
+           double delta, hipStream_t st, mfq_solve_stats* stats) {
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  const Shape sh = default_shape(n);
+  const double mk = -h->lat.kappa;
+  const double tol2 = P->tol * P->tol;
+  const double delta2 = delta * delta;
+  const int nb_half = (g.vh + sh.sb - 1) / sh.sb;
+  const int nb_full = (2 * g.vh + sh.sb - 1) / sh.sb;
+  CgScalars* sc = (CgScalars*)w.sc.ptr;
+  Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), r64 = w.r64.view(g), t64 = w.t64.view(g);
+
+  // initial state: x = 0, r = b, p = r
+  HIPCHK(launch_init_residual(g, b64, r64, part_slot(h, 0), n, sh, st));
+  Partials p0{part_slot(h, 0), nb_full};
+  HIPCHK(launch_finish(FIN_INIT, &p0, 1, n, sc, nullptr, tol2, delta2, st));
+  HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, field_chunks<double>(g, n) * sizeof(d2), st));
+  HIPCHK(hipMemsetAsync(in.x.data, 0, field_chunks<SX>(g, n) * sizeof(typename Store<SX>::chunk), st));
+  if (sizeof(SX) == 2) HIPCHK(hipMemsetAsync(in.x.norm, 0, (size_t)n * 2 * g.vh * sizeof(float), st));
+  HIPCHK(launch_restart<S>(g, r64, in.r, in.p, 1, sc, n, sh, st));
+
+  HopArgs<S, SX> a = hop_args<S, SX>(h, in.L, n);
+  a.sc = sc;
+  a.coef = mk;
+  HopArgs<double, double> a64 = hop_args<double, double>(h, links_d(h), n);
+  a64.sc = sc;
+  a64.coef = mk;
+
+  auto iteration = [&]() -> int {
+    // t = D p (both parities), partial |t|^2 = p^+ D^+ D p
+    a.in = a.self = in.p;
+    a.out = in.t;
+    a.dagger = 0;
+    a.skip_state = ST_CHECK;
+    a.par = 0;
+    a.part = part_slot(h, 0);
+    HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+    a.par = 1;
+    a.part = part_slot(h, 1);
+    HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+    Partials pa[2] = {{part_slot(h, 0), nb_half}, {part_slot(h, 1), nb_half}};
+    HIPCHK(launch_finish(FIN_ALPHA, pa, 2, n, sc, nullptr, tol2, delta2, st));
+    // Ap = D^+ t; r -= alpha Ap; x += alpha p; partial |r|^2
+    a.in = a.self = in.t;
+    a.out = in.r;
+    a.x = in.x;
+    a.p = in.p;
+    a.dagger = 1;
+    a.par = 0;
+    a.part = part_slot(h, 2);
+    HIPCHK(launch_hop<S, SX>(EPI_CGUPD, a, sh, st));
+    a.par = 1;
+    a.part = part_slot(h, 3);
+    HIPCHK(launch_hop<S, SX>(EPI_CGUPD, a, sh, st));
+    Partials pb[2] = {{part_slot(h, 2), nb_half}, {part_slot(h, 3), nb_half}};
+    HIPCHK(launch_finish(FIN_BETA, pb, 2, n, sc, nullptr, tol2, delta2, st));
+    HIPCHK(launch_xpay_p<S>(g, in.r, in.p, sc, n, sh, st));
+    return MFQ_OK;
+  };
+
+  // fold the correction into x64, recompute r64 = b - A x64 in FP64, and
+  // restart the inner recursion from it (RHS that meet tol become DONE)
+  auto reliable_update = [&]() -> int {
+    HIPCHK(launch_fold<SX>(g, in.x, x64, sc, n, sh, st));
+    a64.skip_state = ST_DONE;
+    a64.in = a64.self = x64;
+    a64.out = t64;
+    a64.dagger = 0;
+    a64.part = nullptr;
+    a64.par = 0;
+    HIPCHK(launch_hop<double, double>(EPI_D, a64, sh, st));
+    a64.par = 1;
+    HIPCHK(launch_hop<double, double>(EPI_D, a64, sh, st));
+    a64.in = a64.self = t64;
+    a64.bvec = b64;
+    a64.r64 = r64;
+    a64.dagger = 1;
+    a64.par = 0;
+    a64.part = part_slot(h, 0);
+    HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh, st));
+    a64.par = 1;
+    a64.part = part_slot(h, 1);
+    HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh, st));
+    Partials pt[2] = {{part_slot(h, 0), nb_half}, {part_slot(h, 1), nb_half}};
+    HIPCHK(launch_finish(FIN_TRUE, pt, 2, n, sc, nullptr, tol2, delta2, st));
+    HIPCHK(launch_restart<S>(g, r64, in.r, in.p, set_p_on_update, sc, n, sh, st));
+    return MFQ_OK;
+  };
+
+  const int check_every = P->check_every > 0 ? P->check_every : 16;
+  int total = 0;
+  int rc;
+  bool converged = false;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(w.host_sc, sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool all_done = true, need_update = false;
+    int max_it = 0;
+    for (int r = 0; r < n; ++r) {
+      const CgScalars& s = w.host_sc[r];
+      all_done = all_done && s.state == ST_DONE;
+      need_update = need_update || s.state == ST_CHECK || s.upd;
+      if (s.state != ST_DONE && s.iters > max_it) max_it = s.iters;
+    }
+    if (all_done) {
+      converged = true;
+      break;
+    }
+    if (need_update) {
+      if ((rc = reliable_update()) != MFQ_OK) return rc;
+      continue;
+    }
+    if (max_it >= P->max_iter) {
+      if ((rc = reliable_update()) != MFQ_OK) return rc;
+      HIPCHK(hipMemcpyAsync(w.host_sc, sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      break;
+    }
+    const int k = check_every < P->max_iter - max_it ? check_every : P->max_iter - max_it;
+    for (int i = 0; i < k; ++i)
+      if ((rc = iteration()) != MFQ_OK) return rc;
+    total += k;
+  }
+  (void)total;
+  int status = MFQ_OK;
+  for (int r = 0; r < n; ++r) {
+    const CgScalars& s = w.host_sc[r];
+    if (stats) {
+      stats[r].iters = s.iters;
+      stats[r].reliable_updates = s.n_true;
+      stats[r].true_rel_resid = s.bnorm2 > 0 ? sqrt(s.rtrue2 / s.bnorm2) : 0.0;
+      stats[r].status = s.state == ST_DONE ? MFQ_OK : MFQ_NOT_CONVERGED;
+    }
+    if (s.state != ST_DONE) status = MFQ_NOT_CONVERGED;
+  }
+  (void)converged;
+  return status;
+}
+
+int check_params(const mfq_solve_params* P) {
+  if (!P) return fail(MFQ_ERR_ARG, "params is NULL");
+  if (!(P->tol > 0.0) || P->tol >= 1.0) return fail(MFQ_ERR_ARG, "tol must be in (0, 1)");
+  if (P->max_iter < 1) return fail(MFQ_ERR_ARG, "max_iter must be >= 1");
+  if (P->prec < MFQ_PREC_FP64 || P->prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
+  if (P->precond != MFQ_PC_NONE) return fail(MFQ_ERR_ARG, "preconditioner not available in this call");
+  return MFQ_OK;
+}
+
+// Solve D^+D x64 = b64 for n RHS at the requested precision.
+int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  const double delta = P->reliable_delta > 0.0 ? P->reliable_delta : 0.1;
+  switch (P->prec) {
+    case MFQ_PREC_FP64: {
+      HIPCHK(w.xd.alloc(g, n));
+      HIPCHK(w.rd.alloc(g, n));
+      HIPCHK(w.pd.alloc(g, n));
+      HIPCHK(w.td.alloc(g, n));
+      InnerFields<double, double> in{links_d(h), w.rd.view(g), w.pd.view(g), w.td.view(g), w.xd.view(g)};
+      // FP64: no reliable updates; the true residual is checked at the end
+      return run_cg<double, double>(h, n, P, in, 1, 0.0, st, stats);
+    }
+    case MFQ_PREC_FP32_RELIABLE: {
+      HIPCHK(w.xs.alloc(g, n));
+      HIPCHK(w.rs.alloc(g, n));
+      HIPCHK(w.ps.alloc(g, n));
+      HIPCHK(w.ts.alloc(g, n));
+      InnerFields<float, float> in{links_f(h), w.rs.view(g), w.ps.view(g), w.ts.view(g), w.xs.view(g)};
+      return run_cg<float, float>(h, n, P, in, 0, delta, st, stats);
+    }
+    default: {
+      HIPCHK(w.xs.alloc(g, n));
+      HIPCHK(w.rh.alloc(g, n));
+      HIPCHK(w.ph.alloc(g, n));
+      HIPCHK(w.th.alloc(g, n));
+      InnerFields<_Float16, float> in{links_h(h), w.rh.view(g), w.ph.view(g), w.th.view(g), w.xs.view(g)};
+      return run_cg<_Float16, float>(h, n, P, in, 1, delta, st, stats);
+    }
+  }
+}
+
+int ensure_fp64_fields(mfq_handle* h, int n) {
+  Workspace& w = h->ws;
+  HIPCHK(w.b64.alloc(h->g, n));
+  HIPCHK(w.x64.alloc(h->g, n));
+  HIPCHK(w.r64.alloc(h->g, n));
+  HIPCHK(w.t64.alloc(h->g, n));
+  HIPCHK(w.y64.alloc(h->g, n));
+  return partials_ready(h, n);
+}
+
+int pack_all_links(mfq_handle* h, const double* links_dev, hipStream_t st) {
+  Workspace& w = h->ws;
+  HIPCHK(ensure(w.bad, sizeof(int)));
+  HIPCHK(hipMemsetAsync(w.bad.ptr, 0, sizeof(int), st));
+  HIPCHK(launch_pack_links<double>(h->g, links_dev, (d2*)h->links64.ptr, (int*)w.bad.ptr, st));
+  HIPCHK(launch_pack_links<float>(h->g, links_dev, (f2*)h->links32.ptr, nullptr, st));
+  HIPCHK(launch_pack_links<_Float16>(h->g, links_dev, (h2*)h->links16.ptr, nullptr, st));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, w.bad.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return fail(MFQ_ERR_ARG, "links hold NaN or Inf");
+  return MFQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mfq_last_error(void) { return g_err.c_str(); }
+
+int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mfq_handle** out) {
+  if (!out) return fail(MFQ_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!links_dev) return fail(MFQ_ERR_ARG, "links_dev is NULL");
+  mfq_handle* h = new mfq_handle();
+  h->lat = *lat;
+  Geom& g = h->g;
+  g.lx = lat->dims[0];
+  g.ly = lat->dims[1];
+  g.lz = lat->dims[2];
+  g.bc = lat->bc;
+  g.td = lat->bc == MFQ_BC_SF ? lat->dims[3] - 1 : lat->dims[3];
+  g.t0 = lat->bc == MFQ_BC_SF ? 1 : 0;
+  g.lxh = g.lx / 2;
+  g.vh = g.lxh * g.ly * g.lz * g.td;
+  h->n_slices = lat->bc == MFQ_BC_SF ? lat->dims[3] + 1 : lat->dims[3];
+  const size_t nl = (size_t)2 * 4 * 9 * g.vh;
+  hipError_t e;
+  if ((e = ensure(h->links64, nl * sizeof(d2))) != hipSuccess ||
+      (e = ensure(h->links32, nl * sizeof(f2))) != hipSuccess ||
+      (e = ensure(h->links16, nl * sizeof(h2))) != hipSuccess) {
+    mfq_destroy(h);
+    return fail_hip(e, "allocating links");
+  }
+  if ((e = hipEventCreate(&h->ev0)) != hipSuccess || (e = hipEventCreate(&h->ev1)) != hipSuccess) {
+    mfq_destroy(h);
+    return fail_hip(e, "hipEventCreate");
+  }
+  rc = pack_all_links(h, links_dev, (hipStream_t)stream);
+  if (rc) {
+    mfq_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return MFQ_OK;
+}
+
+int mfq_update_links(mfq_handle* h, const double* links_dev, void* stream) {
+  if (!h || !links_dev) return fail(MFQ_ERR_ARG, "NULL handle or links");
+  return pack_all_links(h, links_dev, (hipStream_t)stream);
+}
+
+int mfq_dslash_prec(mfq_handle* h, int op, int prec, const double* in_dev, double* out_dev, int n_rhs,
+                    void* stream) {
+  if (!h || !in_dev || !out_dev) return fail(MFQ_ERR_ARG, "NULL argument");
+  if (n_rhs < 1) return fail(MFQ_ERR_ARG, "n_rhs must be >= 1");
+  if (op < MFQ_OP_HOP_EO || op > MFQ_OP_HOP_DAG) return fail(MFQ_ERR_ARG, "unknown operator");
+  if (prec < MFQ_PREC_FP64 || prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_fp64_fields(h, n_rhs);
+  if (rc) return rc;
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  const Shape sh = default_shape(n_rhs);
+  HIPCHK(launch_pack_spinor<double>(g, in_dev, w.b64.view(g), n_rhs, 0, nullptr, st));
+  if (prec == MFQ_PREC_FP64) {
+    rc = apply_op<double>(h, op, links_d(h), w.b64.view(g), w.t64.view(g), w.r64.view(g), n_rhs, st);
+  } else if (prec == MFQ_PREC_FP32_RELIABLE) {
+    HIPCHK(w.rs.alloc(g, n_rhs));
+    HIPCHK(w.ps.alloc(g, n_rhs));
+    HIPCHK(w.ts.alloc(g, n_rhs));
+    HIPCHK(launch_convert<double, float>(g, w.b64.view(g), w.rs.view(g), 0, n_rhs, sh, st));
+    rc = apply_op<float>(h, op, links_f(h), w.rs.view(g), w.ts.view(g), w.ps.view(g), n_rhs, st);
+    if (!rc) HIPCHK(launch_convert<float, double>(g, w.ps.view(g), w.r64.view(g), 0, n_rhs, sh, st));
+  } else {
+    HIPCHK(w.rh.alloc(g, n_rhs));
+    HIPCHK(w.ph.alloc(g, n_rhs));
+    HIPCHK(w.th.alloc(g, n_rhs));
+    HIPCHK(launch_convert<double, _Float16>(g, w.b64.view(g), w.rh.view(g), 0, n_rhs, sh, st));
+    rc = apply_op<_Float16>(h, op, links_h(h), w.rh.view(g), w.th.view(g), w.ph.view(g), n_rhs, st);
+    if (!rc) HIPCHK(launch_convert<_Float16, double>(g, w.ph.view(g), w.r64.view(g), 0, n_rhs, sh, st));
+  }
+  if (rc) return rc;
+  HIPCHK(launch_unpack_spinor(g, w.r64.view(g), out_dev, n_rhs, st));
+  return MFQ_OK;
+}
+
+int mfq_dslash(mfq_handle* h, int op, const double* in_dev, double* out_dev, int n_rhs, void* stream) {
+  return mfq_dslash_prec(h, op, MFQ_PREC_FP64, in_dev, out_dev, n_rhs, stream);
+}
+
+int mfq_solve_multi_rhs(mfq_handle* h, const double* b_dev, double* x_dev, int n_rhs,
+                        const mfq_solve_params* params, mfq_solve_stats* stats_host, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!h || !b_dev || !x_dev) return fail(MFQ_ERR_ARG, "NULL argument");
+  if (n_rhs < 1) return fail(MFQ_ERR_ARG, "n_rhs must be >= 1");
+  int rc = check_params(params);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = ensure_fp64_fields(h, n_rhs))) return rc;
+  if ((rc = pack_checked(h, b_dev, n_rhs, 0, st))) return rc;
+  rc = solve_packed(h, n_rhs, params, st, stats_host);
+  if (rc < 0) return rc;
+  HIPCHK(launch_unpack_spinor(h->g, h->ws.x64.view(h->g), x_dev, n_rhs, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats_host)
+    for (int r = 0; r < n_rhs; ++r) stats_host[r].seconds = secs;
+  return rc;
+}
+
+int mfq_fermion_force(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq_solve_params* params,
+                      double* force_dev, double* action_host, double* x_dev, double* y_dev,
+                      mfq_solve_stats* stats_host, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!h || !phi_dev || !force_dev) return fail(MFQ_ERR_ARG, "NULL argument");
+  if (n_rhs < 1) return fail(MFQ_ERR_ARG, "n_rhs must be >= 1");
+  int rc = check_params(params);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = ensure_fp64_fields(h, n_rhs))) return rc;
+  // b = g5 phi;  Z = (D^+D)^-1 b;  Y = g5 Z;  X = D^+ Y
+  if ((rc = pack_checked(h, phi_dev, n_rhs, 1, st))) return rc;
+  rc = solve_packed(h, n_rhs, params, st, stats_host);
+  if (rc < 0) return rc;
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  const Shape sh = default_shape(n_rhs);
+  Field<double> Y = w.y64.view(g), X = w.t64.view(g);
+  HIPCHK(launch_convert<double, double>(g, w.x64.view(g), Y, 1, n_rhs, sh, st));
+  HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n_rhs);
+  a.in = a.self = Y;
+  a.out = X;
+  a.dagger = 1;
+  a.coef = -h->lat.kappa;
+  a.par = 0;
+  HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+  a.par = 1;
+  HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+  const size_t force_bytes = (size_t)4 * h->n_slices * g.lx * g.ly * g.lz * 9 * sizeof(d2);
+  HIPCHK(hipMemsetAsync(force_dev, 0, force_bytes, st));
+  HIPCHK(launch_force(g, links_d(h), X, Y, n_rhs, h->lat.kappa, force_dev, h->n_slices, st));
+  const int nb_full = (2 * g.vh + sh.sb - 1) / sh.sb;
+  HIPCHK(launch_norm2(g, X, part_slot(h, 0), n_rhs, sh, nb_full, st));
+  Partials p0{part_slot(h, 0), nb_full};
+  HIPCHK(launch_finish(FIN_STORE, &p0, 1, n_rhs, nullptr, (double*)w.sums.ptr, 0.0, 0.0, st));
+  if (x_dev) HIPCHK(launch_unpack_spinor(g, X, x_dev, n_rhs, st));
+  if (y_dev) HIPCHK(launch_unpack_spinor(g, Y, y_dev, n_rhs, st));
+  if (action_host)
+    HIPCHK(hipMemcpyAsync(action_host, w.sums.ptr, sizeof(double) * n_rhs, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats_host)
+    for (int r = 0; r < n_rhs; ++r) stats_host[r].seconds = secs;
+  return rc;
+}
+
+int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, double* ms_out) {
+  if (!h || !ms_out) return fail(MFQ_ERR_ARG, "NULL argument");
+  if (n_rhs < 1 || iters < 1) return fail(MFQ_ERR_ARG, "n_rhs and iters must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_fp64_fields(h, n_rhs);
+  if (rc) return rc;
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  const Shape sh = default_shape(n_rhs);
+  auto timed = [&](auto launch) -> int {
+    for (int i = 0; i < 3; ++i) HIPCHK(launch());
+    HIPCHK(hipEventRecord(h->ev0, st));
+    for (int i = 0; i < iters; ++i) HIPCHK(launch());
+    HIPCHK(hipEventRecord(h->ev1, st));
+    HIPCHK(hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    *ms_out = ms / iters;
+    return MFQ_OK;
+  };
+  HIPCHK(hipMemsetAsync(w.b64.data.ptr, 0, field_chunks<double>(g, n_rhs) * sizeof(d2), st));
+  if (prec == MFQ_PREC_FP64) {
+    HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n_rhs);
+    a.in = a.self = w.b64.view(g);
+    a.out = w.r64.view(g);
+    a.coef = -h->lat.kappa;
+    a.part = part_slot(h, 0);
+    return timed([&]() { return launch_hop<double, double>(EPI_D, a, sh, st); });
+  } else if (prec == MFQ_PREC_FP32_RELIABLE) {
+    HIPCHK(w.rs.alloc(g, n_rhs));
+    HIPCHK(w.ts.alloc(g, n_rhs));
+    HIPCHK(launch_convert<double, float>(g, w.b64.view(g), w.rs.view(g), 0, n_rhs, sh, st));
+    HopArgs<float, float> a = hop_args<float, float>(h, links_f(h), n_rhs);
+    a.in = a.self = w.rs.view(g);
+    a.out = w.ts.view(g);
+    a.coef = -h->lat.kappa;
+    a.part = part_slot(h, 0);
+    return timed([&]() { return launch_hop<float, float>(EPI_D, a, sh, st); });
+  } else {
+    HIPCHK(w.rh.alloc(g, n_rhs));
+    HIPCHK(w.th.alloc(g, n_rhs));
+    HIPCHK(launch_convert<double, _Float16>(g, w.b64.view(g), w.rh.view(g), 0, n_rhs, sh, st));
+    HopArgs<_Float16, float> a = hop_args<_Float16, float>(h, links_h(h), n_rhs);
+    a.in = a.self = w.rh.view(g);
+    a.out = w.th.view(g);
+    a.coef = -h->lat.kappa;
+    a.part = part_slot(h, 0);
+    return timed([&]() { return launch_hop<_Float16, float>(EPI_D, a, sh, st); });
+  }
+}
+
+void mfq_destroy(mfq_handle* h) {
+  if (!h) return;
+  Workspace& w = h->ws;
+  for (auto* f : {&w.b64, &w.x64, &w.r64, &w.t64, &w.y64, &w.xd, &w.rd, &w.pd, &w.td}) f->free_all();
+  for (auto* f : {&w.xs, &w.rs, &w.ps, &w.ts}) f->free_all();
+  for (auto* f : {&w.rh, &w.ph, &w.th}) f->free_all();
+  release(w.part);
+  release(w.sc);
+  release(w.sums);
+  release(w.bad);
+  if (w.host_sc) (void)hipHostFree(w.host_sc);
+  release(h->links64);
+  release(h->links32);
+  release(h->links16);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+// Device-side building blocks of the MI355X quark-solve library: complex
+// arithmetic, the even/odd structure-of-arrays field layouts in FP64, FP32 and
+// FP16 (with a per-site norm), the spin projectors of the Wilson hopping term,
+// and the FP64 wavefront/workgroup reductions.
+//
+// Layouts (all "site fastest", so that the 64 lanes of a wavefront touch 64
+// consecutive sites of one right-hand side and every load is coalesced):
+//
+//   spinor chunk array  [rhs][parity][chunk][site]    (16-byte chunks)
+//       FP64: 12 chunks of one complex (double2)
+//       FP32:  6 chunks of two complex (float4)
+//       FP16:  3 chunks of four complex (8 x fp16), plus a norm array
+//              [rhs][parity][site] (fp32): stored value = value / norm,
+//              norm = max |real component| of the 24 reals of the site.
+//   link array          [parity][mu][9][site]  (FP64 double2, FP32 float2,
+//                                               FP16 2 x fp16 per complex)
+//
+// A "site" is a half-lattice index s = xh + (Lx/2)(y + Ly(z + Lz t)) over the
+// dynamical time slices t = 0..Td-1 (x0 = t + 1 under Schroedinger-functional
+// boundaries, x0 = t otherwise); its x coordinate is 2 xh + ((x0+y+z+p) & 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mfq {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct cpx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a) { return {-a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+// a * b
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cpx<T> cjmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a
+template <typename T>
+__device__ __forceinline__ cpx<T> imul(cpx<T> a) { return {-a.im, a.re}; }
+template <typename T>
+__device__ __forceinline__ T norm2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------- geometry
+enum : int { BC_SF = 0, BC_PERIODIC = 1, BC_ANTIPERIODIC = 2 };
+
+struct Geom {
+  int lx, ly, lz, td;  // spatial extents and number of dynamical time slices
+  int lxh;             // lx / 2
+  int vh;              // half volume of the dynamical lattice
+  int t0;              // x0 of the first dynamical slice (1 for SF, else 0)
+  int bc;
+};
+
+struct Coords {
+  int x, y, z, t;
+};
+
+__device__ __forceinline__ Coords site_coords(const Geom& g, int s, int parity) {
+  Coords c;
+  int xh = s % g.lxh;
+  int r = s / g.lxh;
+  c.y = r % g.ly;
+  r /= g.ly;
+  c.z = r % g.lz;
+  c.t = r / g.lz;
+  c.x = 2 * xh + ((c.t + g.t0 + c.y + c.z + parity) & 1);
+  return c;
+}
+
+__device__ __forceinline__ int half_index(const Geom& g, int x, int y, int z, int t) {
+  return (x >> 1) + g.lxh * (y + g.ly * (z + g.lz * t));
+}
+
+// ------------------------------------------------------------- storage traits
+template <typename S>
+struct Store;
+
+template <>
+struct Store<double> {
+  using chunk = d2;
+  static constexpr int NC = 12;
+  using link_elem = d2;
+};
+template <>
+struct Store<float> {
+  using chunk = f4;
+  static constexpr int NC = 6;
+  using link_elem = f2;
+};
+template <>
+struct Store<_Float16> {
+  using chunk = h8;
+  static constexpr int NC = 3;
+  using link_elem = h2;
+};
+
+// A batched spinor field: n_rhs full (both parity) fields.
+template <typename S>
+struct Field {
+  typename Store<S>::chunk* data;
+  float* norm;  // FP16 only
+  int vh;
+  __device__ __forceinline__ long cidx(int rhs, int par, int c, int s) const {
+    return ((long)(rhs * 2 + par) * Store<S>::NC + c) * vh + s;
+  }
+  __device__ __forceinline__ long nidx(int rhs, int par, int s) const {
+    return (long)(rhs * 2 + par) * vh + s;
+  }
+};
+
+template <typename S>
+struct Links {
+  const typename Store<S>::link_elem* data;  // [parity][mu][9][vh]
+  int vh;
+  __device__ __forceinline__ long idx(int par, int mu, int k, int s) const {
+    return ((long)(par * 4 + mu) * 9 + k) * vh + s;
+  }
+};
+
+// Spinor register block: v[3 * spin + colour].
+template <typename T>
+struct Spinor {
+  cpx<T> v[12];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_spinor(const Field<double>& f, int rhs, int par, int s, Spinor<T>& o) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    d2 q = f.data[f.cidx(rhs, par, c, s)];
+    o.v[c] = {(T)q.x, (T)q.y};
+  }
+}
+template <typename T>
+__device__ __forceinline__ void load_spinor(const Field<float>& f, int rhs, int par, int s, Spinor<T>& o) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    f4 q = f.data[f.cidx(rhs, par, c, s)];
+    o.v[2 * c] = {(T)q.x, (T)q.y};
+    o.v[2 * c + 1] = {(T)q.z, (T)q.w};
+  }
+}
+template <typename T>
+__device__ __forceinline__ void load_spinor(const Field<_Float16>& f, int rhs, int par, int s, Spinor<T>& o) {
+  const float n = f.norm[f.nidx(rhs, par, s)];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h8 q = f.data[f.cidx(rhs, par, c, s)];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o.v[4 * c + k] = {(T)((float)q[2 * k] * n), (T)((float)q[2 * k + 1] * n)};
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_spinor(const Field<double>& f, int rhs, int par, int s, const Spinor<T>& o) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    d2 q;
+    q.x = (double)o.v[c].re;
+    q.y = (double)o.v[c].im;
+    f.data[f.cidx(rhs, par, c, s)] = q;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store_spinor(const Field<float>& f, int rhs, int par, int s, const Spinor<T>& o) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    f4 q;
+    q.x = (float)o.v[2 * c].re;
+    q.y = (float)o.v[2 * c].im;
+    q.z = (float)o.v[2 * c + 1].re;
+    q.w = (float)o.v[2 * c + 1].im;
+    f.data[f.cidx(rhs, par, c, s)] = q;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store_spinor(const Field<_Float16>& f, int rhs, int par, int s, const Spinor<T>& o) {
+  float m = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)o.v[c].re), fabsf((float)o.v[c].im)));
+  const float inv = m > 0.f ? 1.0f / m : 0.f;
+  f.norm[f.nidx(rhs, par, s)] = m;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h8 q;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      q[2 * k] = (_Float16)((float)o.v[4 * c + k].re * inv);
+      q[2 * k + 1] = (_Float16)((float)o.v[4 * c + k].im * inv);
+    }
+    f.data[f.cidx(rhs, par, c, s)] = q;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_link(const Links<double>& l, int par, int mu, int s, cpx<T> u[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    d2 q = l.data[l.idx(par, mu, k, s)];
+    u[k] = {(T)q.x, (T)q.y};
+  }
+}
+template <typename T>
+__device__ __forceinline__ void load_link(const Links<float>& l, int par, int mu, int s, cpx<T> u[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    f2 q = l.data[l.idx(par, mu, k, s)];
+    u[k] = {(T)q.x, (T)q.y};
+  }
+}
+template <typename T>
+__device__ __forceinline__ void load_link(const Links<_Float16>& l, int par, int mu, int s, cpx<T> u[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    h2 q = l.data[l.idx(par, mu, k, s)];
+    u[k] = {(T)(float)q.x, (T)(float)q.y};
+  }
+}
+
+// -------------------------------------------------- Wilson hopping algebra
+// Chiral basis: g_mu = [[0, e_mu], [e_mu^+, 0]], e_0 = -1, e_k = -i sigma_k.
+// (1 + sg g_mu) psi = [h ; sg e_mu^+ h] with h = psi_up + sg e_mu psi_down, so
+// only the 2-spin "half spinor" h travels through the colour multiply.
+
+// h = psi_up + sg * e_mu psi_down   (colour index a)
+template <int MU, typename T>
+__device__ __forceinline__ void project(const Spinor<T>& p, T sg, int a, cpx<T>& h0, cpx<T>& h1) {
+  const cpx<T> u0 = p.v[a], u1 = p.v[3 + a], d0 = p.v[6 + a], d1 = p.v[9 + a];
+  if constexpr (MU == 0) {  // e d = (-d0, -d1)
+    h0 = u0 - sg * d0;
+    h1 = u1 - sg * d1;
+  } else if constexpr (MU == 1) {  // e d = (-i d1, -i d0)
+    h0 = u0 - sg * imul(d1);
+    h1 = u1 - sg * imul(d0);
+  } else if constexpr (MU == 2) {  // e d = (-d1, d0)
+    h0 = u0 - sg * d1;
+    h1 = u1 + sg * d0;
+  } else {  // e d = (-i d0, i d1)
+    h0 = u0 - sg * imul(d0);
+    h1 = u1 + sg * imul(d1);
+  }
+}
+
+// acc += [g ; sg e_mu^+ g]   (colour index a)
+template <int MU, typename T>
+__device__ __forceinline__ void reconstruct(Spinor<T>& acc, T sg, int a, cpx<T> g0, cpx<T> g1) {
+  acc.v[a] = acc.v[a] + g0;
+  acc.v[3 + a] = acc.v[3 + a] + g1;
+  if constexpr (MU == 0) {  // e^+ g = (-g0, -g1)
+    acc.v[6 + a] = acc.v[6 + a] - sg * g0;
+    acc.v[9 + a] = acc.v[9 + a] - sg * g1;
+  } else if constexpr (MU == 1) {  // e^+ g = (i g1, i g0)
+    acc.v[6 + a] = acc.v[6 + a] + sg * imul(g1);
+    acc.v[9 + a] = acc.v[9 + a] + sg * imul(g0);
+  } else if constexpr (MU == 2) {  // e^+ g = (g1, -g0)
+    acc.v[6 + a] = acc.v[6 + a] + sg * g1;
+    acc.v[9 + a] = acc.v[9 + a] - sg * g0;
+  } else {  // e^+ g = (i g0, -i g1)
+    acc.v[6 + a] = acc.v[6 + a] + sg * imul(g0);
+    acc.v[9 + a] = acc.v[9 + a] - sg * imul(g1);
+  }
+}
+
+// ---------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace mfq

@@ -1,0 +1,264 @@
+// Canonical FP64 boundary layout <-> internal even/odd SoA layout, and the
+// fermion MD force.
+//
+// Canonical spinor: [rhs][t][z][y][x][spin 4][colour 3] complex128 over the
+// dynamical slices; canonical links and force: [mu][x0][z][y][x][3][3]
+// complex128 over the stored link slices (x0 = 0..T for SF, 0..T-1 else).
+#include "internal.h"
+
+namespace mfq {
+
+template <typename S>
+struct CT {
+  using T = float;
+};
+template <>
+struct CT<double> {
+  using T = double;
+};
+
+__device__ __forceinline__ void canon_coords(const Geom& g, int q, int& x, int& y, int& z, int& t) {
+  x = q % g.lx;
+  int r = q / g.lx;
+  y = r % g.ly;
+  r /= g.ly;
+  z = r % g.lz;
+  t = r / g.lz;
+}
+
+template <typename S>
+__global__ void pack_spinor_kernel(Geom g, const d2* canon, Field<S> f, int n_rhs, int gamma5, int* bad) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const int vd = 2 * g.vh;
+  if (q >= vd || r >= n_rhs) return;
+  int x, y, z, t;
+  canon_coords(g, q, x, y, z, t);
+  const int par = (x + y + z + t + g.t0) & 1;
+  const d2* src = canon + ((long)r * vd + q) * 12;
+  using T = typename CT<S>::T;
+  Spinor<T> o;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    d2 v = src[k];
+    finite = finite && isfinite(v.x) && isfinite(v.y);
+    const double sg = (gamma5 && k >= 6) ? -1.0 : 1.0;
+    o.v[k] = {(T)(sg * v.x), (T)(sg * v.y)};
+  }
+  if (!finite && bad) atomicOr(bad, 1);
+  store_spinor(f, r, par, half_index(g, x, y, z, t), o);
+}
+
+__global__ void unpack_spinor_kernel(Geom g, Field<double> f, d2* canon, int n_rhs) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const int vd = 2 * g.vh;
+  if (q >= vd || r >= n_rhs) return;
+  int x, y, z, t;
+  canon_coords(g, q, x, y, z, t);
+  const int par = (x + y + z + t + g.t0) & 1;
+  Spinor<double> o;
+  load_spinor(f, r, par, half_index(g, x, y, z, t), o);
+  d2* dst = canon + ((long)r * vd + q) * 12;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    d2 v;
+    v.x = o.v[k].re;
+    v.y = o.v[k].im;
+    dst[k] = v;
+  }
+}
+
+// Links on the dynamical sites only: U_mu(n) for every dynamical n, mu.
+template <typename S>
+__global__ void pack_links_kernel(Geom g, const d2* canon, typename Store<S>::link_elem* out, int* bad) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mu = blockIdx.y;
+  const int vd = 2 * g.vh;
+  if (q >= vd) return;
+  int x, y, z, t;
+  canon_coords(g, q, x, y, z, t);
+  const int par = (x + y + z + t + g.t0) & 1;
+  const int s = half_index(g, x, y, z, t);
+  const long n_slice_sites = (long)g.lx * g.ly * g.lz;
+  const int n_slices = g.td + (g.bc == BC_SF ? 2 : 0);
+  const d2* src = canon + (((long)mu * n_slices + (t + g.t0)) * n_slice_sites + q % n_slice_sites) * 9;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    d2 v = src[k];
+    finite = finite && isfinite(v.x) && isfinite(v.y);
+    typename Store<S>::link_elem e;
+    e.x = (S)v.x;
+    e.y = (S)v.y;
+    out[((long)(par * 4 + mu) * 9 + k) * g.vh + s] = e;
+  }
+  if (!finite && bad) atomicOr(bad, 1);
+}
+
+template <typename S>
+hipError_t launch_pack_spinor(const Geom& g, const double* canon, Field<S> f, int n_rhs, int gamma5, int* bad,
+                              hipStream_t st) {
+  dim3 grid((2 * g.vh + 255) / 256, n_rhs);
+  hipLaunchKernelGGL((pack_spinor_kernel<S>), grid, dim3(256), 0, st, g, (const d2*)canon, f, n_rhs, gamma5, bad);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_spinor(const Geom& g, Field<double> f, double* canon, int n_rhs, hipStream_t st) {
+  dim3 grid((2 * g.vh + 255) / 256, n_rhs);
+  hipLaunchKernelGGL(unpack_spinor_kernel, grid, dim3(256), 0, st, g, f, (d2*)canon, n_rhs);
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_pack_links(const Geom& g, const double* canon, typename Store<S>::link_elem* out, int* bad,
+                             hipStream_t st) {
+  dim3 grid((2 * g.vh + 255) / 256, 4);
+  hipLaunchKernelGGL((pack_links_kernel<S>), grid, dim3(256), 0, st, g, (const d2*)canon, out, bad);
+  return hipGetLastError();
+}
+
+template hipError_t launch_pack_spinor<double>(const Geom&, const double*, Field<double>, int, int, int*, hipStream_t);
+template hipError_t launch_pack_spinor<float>(const Geom&, const double*, Field<float>, int, int, int*, hipStream_t);
+template hipError_t launch_pack_spinor<_Float16>(const Geom&, const double*, Field<_Float16>, int, int, int*, hipStream_t);
+template hipError_t launch_pack_links<double>(const Geom&, const double*, d2*, int*, hipStream_t);
+template hipError_t launch_pack_links<float>(const Geom&, const double*, f2*, int*, hipStream_t);
+template hipError_t launch_pack_links<_Float16>(const Geom&, const double*, h2*, int*, hipStream_t);
+
+// ------------------------------------------------------------------ force
+// For the link (n, mu), with X = D^-1 phi and Y = (D^+)^-1 X per RHS i:
+//   A = sum_i sum_b h-[X_i(n+mu)]_b h-[Y_i(n)]_b^+ ,  h-[psi] = psi_up - e_mu psi_down
+//   B = sum_i sum_b h+[X_i(n)]_b h+[Y_i(n+mu)]_b^+ ,  h+[psi] = psi_up + e_mu psi_down
+//   M = U A - B U^+,   G = -kappa ( (M - M^+)/(2i) - Tr(...)/3 )
+// which is Eq. 3's f[x_i, y_i] summed over i, with the RHS sum taken before
+// the colour multiplications (the force is linear in the outer products).
+template <int MU>
+__device__ __forceinline__ void force_link(const Geom& g, const Links<double>& L, const Field<double>& X,
+                                           const Field<double>& Y, int n_rhs, double kappa, int par, int s,
+                                           const Coords& c, d2* out) {
+  int x = c.x, y = c.y, z = c.z, t = c.t;
+  double sgn = 1.0;
+  bool ok = true;
+  if constexpr (MU == 0) {
+    t = c.t + 1;
+    if (t == g.td) {
+      if (g.bc == BC_SF) ok = false;
+      t = 0;
+      if (g.bc == BC_ANTIPERIODIC) sgn = -1.0;
+    }
+  } else if constexpr (MU == 1) {
+    x = (c.x + 1 == g.lx) ? 0 : c.x + 1;
+  } else if constexpr (MU == 2) {
+    y = (c.y + 1 == g.ly) ? 0 : c.y + 1;
+  } else {
+    z = (c.z + 1 == g.lz) ? 0 : c.z + 1;
+  }
+  cpx<double> G[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) G[k] = {0.0, 0.0};
+  if (ok) {
+    const int sf = half_index(g, x, y, z, t);
+    const int po = 1 - par;
+    cpx<double> A[9], B[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = B[k] = {0.0, 0.0};
+    for (int r = 0; r < n_rhs; ++r) {
+      Spinor<double> xf, yn, xn, yf;
+      load_spinor(X, r, po, sf, xf);
+      load_spinor(Y, r, par, s, yn);
+      load_spinor(X, r, par, s, xn);
+      load_spinor(Y, r, po, sf, yf);
+      cpx<double> hx0[3], hx1[3], hy0[3], hy1[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        project<MU>(xf, -1.0, k, hx0[k], hx1[k]);
+        project<MU>(yn, -1.0, k, hy0[k], hy1[k]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          A[3 * a + b] = A[3 * a + b] + cjmul(hy0[b], hx0[a]) + cjmul(hy1[b], hx1[a]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        project<MU>(xn, 1.0, k, hx0[k], hx1[k]);
+        project<MU>(yf, 1.0, k, hy0[k], hy1[k]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          B[3 * a + b] = B[3 * a + b] + cjmul(hy0[b], hx0[a]) + cjmul(hy1[b], hx1[a]);
+    }
+    cpx<double> u[9];
+    load_link(L, par, MU, s, u);
+    cpx<double> M[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        cpx<double> ua = {0.0, 0.0}, bu = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          ua = ua + cmul(u[3 * a + k], A[3 * k + b]);
+          bu = bu + cjmul(u[3 * b + k], B[3 * a + k]);  // B_{ak} conj(U_{bk}) = (B U^+)_{ab}
+        }
+        M[3 * a + b] = sgn * (ua - bu);
+      }
+    // H = (M - M^+) / (2i): H_ab = (M_ab - conj(M_ba)) / (2i)
+    cpx<double> H[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const cpx<double> d = {M[3 * a + b].re - M[3 * b + a].re, M[3 * a + b].im + M[3 * b + a].im};
+        H[3 * a + b] = {0.5 * d.im, -0.5 * d.re};
+      }
+    const double tr3 = (H[0].re + H[4].re + H[8].re) / 3.0;
+    H[0].re -= tr3;
+    H[4].re -= tr3;
+    H[8].re -= tr3;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G[k] = (-kappa) * H[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    d2 v;
+    v.x = G[k].re;
+    v.y = G[k].im;
+    out[k] = v;
+  }
+}
+
+__global__ void force_kernel(Geom g, Links<double> L, Field<double> X, Field<double> Y, int n_rhs, double kappa,
+                             d2* out, int n_slices) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // canonical dynamical site
+  const int mu = blockIdx.y;
+  if (q >= 2 * g.vh) return;
+  int x, y, z, t;
+  canon_coords(g, q, x, y, z, t);
+  const int par = (x + y + z + t + g.t0) & 1;
+  const int s = half_index(g, x, y, z, t);
+  Coords c;
+  c.x = x;
+  c.y = y;
+  c.z = z;
+  c.t = t;
+  const long n_slice_sites = (long)g.lx * g.ly * g.lz;
+  d2* dst = out + (((long)mu * n_slices + (t + g.t0)) * n_slice_sites + q % n_slice_sites) * 9;
+  switch (mu) {
+    case 0: force_link<0>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
+    case 1: force_link<1>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
+    case 2: force_link<2>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
+    default: force_link<3>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
+  }
+}
+
+hipError_t launch_force(const Geom& g, Links<double> links, Field<double> X, Field<double> Y, int n_rhs,
+                        double kappa, double* force_canon, int n_link_slices, hipStream_t st) {
+  dim3 grid((2 * g.vh + 127) / 128, 4);
+  hipLaunchKernelGGL(force_kernel, grid, dim3(128), 0, st, g, links, X, Y, n_rhs, kappa, (d2*)force_canon,
+                     n_link_slices);
+  return hipGetLastError();
+}
+
+}  // namespace mfq
