@@ -134,7 +134,12 @@ def main():
     if not args.no_bandwidth:
         dims = tuple(int(v) for v in args.bw_dims.split(","))
         print(f"[bench] bandwidth lattice {dims}", file=sys.stderr, flush=True)
-        ub = synth.random_links(dims, "periodic", 0.3, 7)
+        # random SU(3) links on a 16^3 x 8 block, tiled over the lattice: the
+        # values do not matter for bandwidth and numpy's 3x3 eigh is slow
+        blk = (min(16, dims[0]), min(16, dims[1]), min(16, dims[2]), min(8, dims[3]))
+        ub = synth.random_links(blk, "periodic", 0.3, 7)
+        reps = (1, dims[3] // blk[3], dims[2] // blk[2], dims[1] // blk[1], dims[0] // blk[0], 1, 1)
+        ub = np.ascontiguousarray(np.tile(ub, reps))
         big = mfq.Lattice(dims, "periodic", 0.12, torch.from_numpy(ub).to(dev))
         del ub
         bw = {}

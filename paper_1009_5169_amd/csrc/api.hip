@@ -62,6 +62,14 @@ struct Workspace {
   int host_cap = 0;
 };
 
+// A captured run of k inner CG iterations.  The key holds everything the
+// captured kernel arguments depend on, so a stale graph never matches.
+struct GraphEntry {
+  std::vector<uintptr_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct mfq_handle {
   mfq_lattice lat;
   Geom g;
@@ -69,7 +77,24 @@ struct mfq_handle {
   DevBuf links64, links32, links16;
   Workspace ws;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t cap_stream = nullptr;  // used only to capture graphs
+  std::vector<GraphEntry> graphs;
 };
+
+namespace {
+uintptr_t bits(double v) {
+  uint64_t u;
+  memcpy(&u, &v, sizeof(u));
+  return (uintptr_t)u;
+}
+void drop_graphs(mfq_handle* h) {
+  for (auto& e : h->graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+  }
+  h->graphs.clear();
+}
+}  // namespace
 
 namespace {
 
@@ -236,7 +261,8 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   a64.sc = sc;
   a64.coef = mk;
 
-  auto iteration = [&]() -> int {
+  int rc_ = MFQ_OK;
+  auto iteration = [&](hipStream_t st) -> int {
     // t = D p (both parities), partial |t|^2 = p^+ D^+ D p
     a.in = a.self = in.p;
     a.out = in.t;
@@ -297,27 +323,74 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     return MFQ_OK;
   };
 
-  const int check_every = P->check_every > 0 ? P->check_every : 16;
+  // k iterations, replayed from a captured graph when allowed: the graph is
+  // captured on the handle's own stream and launched on the caller's
+  auto run_iters = [&](int k) -> int {
+    if (!P->use_graph) {
+      for (int i = 0; i < k; ++i)
+        if ((rc_ = iteration(st)) != MFQ_OK) return rc_;
+      return MFQ_OK;
+    }
+    std::vector<uintptr_t> key = {(uintptr_t)sizeof(S), (uintptr_t)sizeof(SX), (uintptr_t)n, (uintptr_t)k,
+                                  (uintptr_t)in.r.data, (uintptr_t)in.p.data, (uintptr_t)in.t.data,
+                                  (uintptr_t)in.x.data, (uintptr_t)in.L.data, (uintptr_t)w.part.ptr,
+                                  (uintptr_t)sc, bits(tol2), bits(delta2)};
+    GraphEntry* hit = nullptr;
+    for (auto& e : h->graphs)
+      if (e.key == key) hit = &e;
+    if (!hit) {
+      if (h->graphs.size() >= 24) drop_graphs(h);
+      GraphEntry e;
+      e.key = key;
+      HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc2 = MFQ_OK;
+      for (int i = 0; i < k && rc2 == MFQ_OK; ++i) rc2 = iteration(h->cap_stream);
+      hipError_t ec = hipStreamEndCapture(h->cap_stream, &e.graph);
+      if (rc2 != MFQ_OK) return rc2;
+      HIPCHK(ec);
+      HIPCHK(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+      h->graphs.push_back(e);
+      hit = &h->graphs.back();
+    }
+    HIPCHK(hipGraphLaunch(hit->exec, st));
+    return MFQ_OK;
+  };
+
+  // Poll interval: predicted iterations to convergence of the slowest RHS from
+  // the last interval's contraction rate, rounded to a power of two (so only a
+  // few graph sizes exist), within [min_k, max_k].
+  const int max_k = P->check_every > 0 ? P->check_every : 64;
+  const int min_k = max_k < 4 ? max_k : 4;
+  int k = min_k;
+  std::vector<double> rho_prev(n, 0.0);
   int total = 0;
   int rc;
-  bool converged = false;
   for (;;) {
     HIPCHK(hipMemcpyAsync(w.host_sc, sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool all_done = true, need_update = false;
     int max_it = 0;
+    double want = 0.0;
     for (int r = 0; r < n; ++r) {
       const CgScalars& s = w.host_sc[r];
       all_done = all_done && s.state == ST_DONE;
       need_update = need_update || s.state == ST_CHECK || s.upd;
       if (s.state != ST_DONE && s.iters > max_it) max_it = s.iters;
+      if (s.state == ST_ACTIVE && rho_prev[r] > 0.0 && s.rho < rho_prev[r] && total > 0) {
+        // iterations until rho <= min(tol^2, delta^2 rho_ru) at the observed rate
+        const double rate = log(s.rho / rho_prev[r]) / k;
+        double target = tol2 * s.bnorm2;
+        if (delta2 > 0.0 && delta2 * s.rho_ru > target) target = delta2 * s.rho_ru;
+        const double it = log(target / s.rho) / rate;
+        if (it > want) want = it;
+      }
+      rho_prev[r] = s.state == ST_ACTIVE ? s.rho : 0.0;
     }
-    if (all_done) {
-      converged = true;
-      break;
-    }
+    if (all_done) break;
     if (need_update) {
       if ((rc = reliable_update()) != MFQ_OK) return rc;
+      for (int r = 0; r < n; ++r) rho_prev[r] = 0.0;
+      k = min_k;
       continue;
     }
     if (max_it >= P->max_iter) {
@@ -326,12 +399,15 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
       HIPCHK(hipStreamSynchronize(st));
       break;
     }
-    const int k = check_every < P->max_iter - max_it ? check_every : P->max_iter - max_it;
-    for (int i = 0; i < k; ++i)
-      if ((rc = iteration()) != MFQ_OK) return rc;
+    if (total > 0) {
+      int kk = min_k;
+      while (kk < max_k && kk * 2 <= (int)(want + 1.0)) kk *= 2;
+      k = kk;
+    }
+    if (k > P->max_iter - max_it) k = P->max_iter - max_it;
+    if ((rc = run_iters(k)) != MFQ_OK) return rc;
     total += k;
   }
-  (void)total;
   int status = MFQ_OK;
   for (int r = 0; r < n; ++r) {
     const CgScalars& s = w.host_sc[r];
@@ -343,7 +419,6 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     }
     if (s.state != ST_DONE) status = MFQ_NOT_CONVERGED;
   }
-  (void)converged;
   return status;
 }
 
@@ -446,7 +521,8 @@ int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mf
     mfq_destroy(h);
     return fail_hip(e, "allocating links");
   }
-  if ((e = hipEventCreate(&h->ev0)) != hipSuccess || (e = hipEventCreate(&h->ev1)) != hipSuccess) {
+  if ((e = hipEventCreate(&h->ev0)) != hipSuccess || (e = hipEventCreate(&h->ev1)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
     mfq_destroy(h);
     return fail_hip(e, "hipEventCreate");
   }
@@ -634,6 +710,8 @@ void mfq_destroy(mfq_handle* h) {
   release(h->links64);
   release(h->links32);
   release(h->links16);
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   delete h;
