@@ -30,13 +30,14 @@ def hop_bytes_per_site_rhs(prec: str, n_rhs: int) -> float:
     """Algorithmic HBM bytes of the fused half-dslash D-epilogue kernel per
     output site per RHS: the other-parity input read once, the same-parity
     input read once, the output written once, and the 8 links of the site
-    (each link is read once per launch) shared by the n_rhs RHS."""
+    (each link is read once per launch) shared by the n_rhs RHS.  FP64 links
+    are 18 reals; the FP32 / FP16 copies store two rows (12 reals)."""
     if prec == "fp64":
         spinor, link = 24 * 8, 18 * 8
     elif prec == "fp32":
-        spinor, link = 24 * 4, 18 * 4
+        spinor, link = 24 * 4, 12 * 4
     else:  # fp16 values + one fp32 norm per site
-        spinor, link = 24 * 2 + 4, 18 * 2
+        spinor, link = 24 * 2 + 4, 12 * 2
     return 3 * spinor + 8 * link / n_rhs
 
 
@@ -49,6 +50,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bandwidth", action="store_true")
     ap.add_argument("--bw-dims", default="32,32,32,64")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the batch, FP16 and learned-preconditioner measurements")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only launch the roofline kernel (solve shape) and a 1 GiB copy, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the pseudo-fermion "
@@ -63,6 +68,9 @@ def main():
 
     dev = "cuda:0"
     p = synth.CONFIG_1
+    if args.profile_kernels:
+        profile_kernels(args, synth, mfq, torch, dev)
+        return
     u = p.links()
     phi_h = p.rhs()
     lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(u).to(dev))
@@ -156,6 +164,12 @@ def main():
         big.close()
         torch.cuda.empty_cache()
 
+    if not args.no_rows:
+        out["rows"] = {}
+        out["rows"]["fp16_16x16x16x16"] = bench_fp16(synth, mfq, torch, dev, np)
+        out["rows"]["learned_16x16x16x16"] = bench_learned(synth, mfq, torch, dev, np)
+        out["rows"]["batch_64_lattices"] = bench_batch(synth, mfq, torch, dev, np)
+
     if not args.no_cpu_baseline:
         from oracle import force as fmod
         from oracle import native
@@ -175,6 +189,135 @@ def main():
                                          "FP64 CG solves (normal equations, tol 1e-10) and the force"}
     lat.close()
     print(json.dumps(out))
+
+
+def _timed(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        res = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / reps, res
+
+
+def bench_fp16(synth, mfq, torch, dev, np):
+    """16^3x16 SF, eps = 0.5, kappa = 0.135, 5 RHS: FP16 storage (per-site norm)
+    with FP64 defect correction against FP32 and plain FP64 CG, to 1e-10."""
+    p = synth.CONFIG_2
+    print(f"[bench] row fp16 {p.name}", file=sys.stderr, flush=True)
+    lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
+    b = torch.from_numpy(p.rhs()).to(dev)
+    res = {"workload": p.name, "tol": 1e-10}
+    xs = {}
+    for prec in ("fp64", "fp32", "fp16"):
+        pr = mfq.make_params(tol=1e-10, prec=prec, max_iter=50000)
+        ms, (x, st, rc) = _timed(lambda: lat.solve(b, params=pr))
+        xs[prec] = x.cpu().numpy()
+        res[prec] = {"ms": round(ms, 3), "rc": rc, "iters": [s["iters"] for s in st],
+                     "true_rel_resid_max": max(s["true_rel_resid"] for s in st)}
+    for prec in ("fp32", "fp16"):
+        res[prec]["rel_err_vs_fp64_path"] = float(np.linalg.norm(xs[prec] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+    lat.close()
+    return res
+
+
+def bench_learned(synth, mfq, torch, dev, np):
+    """16^3x16 SF, eps = 0.5, kappa = 0.1375, 5 evaluation RHS: train the PTC
+    network on CG pairs from training RHS (seeds 6000+), then FGMRES(16) with
+    it, FGMRES(16) without it and plain FP64 CG, all to 1e-10."""
+    p = synth.CONFIG_4
+    print(f"[bench] row learned {p.name}", file=sys.stderr, flush=True)
+    lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
+    b = torch.from_numpy(p.rhs()).to(dev)
+    tb = torch.from_numpy(synth.gaussian_spinors(p.dims, p.bc, 4, synth.PTC_TRAIN_SEED)).to(dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r, e = lat.precond_pairs(tb, every=25, n_snap=4)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t
+    lat.precond_init(seed=1)
+    t = time.perf_counter()
+    hist = lat.precond_train(r, e, steps=300, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    res = {"workload": p.name, "tol": 1e-10, "pairs": int(r.shape[0]), "train_steps": 300,
+           "pairs_s": round(t_pairs, 3), "train_s": round(t_train, 3),
+           "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
+    xs = {}
+    for name, kw in (("cg_fp64", dict(prec="fp64")), ("fgmres_identity", dict(prec="fp64", precond="identity")),
+                     ("fgmres_ptc", dict(prec="fp64", precond="ptc"))):
+        pr = mfq.make_params(tol=1e-10, max_iter=50000, **kw)
+        ms, (x, st, rc) = _timed(lambda: lat.solve(b, params=pr), reps=2)
+        xs[name] = x.cpu().numpy()
+        res[name] = {"ms": round(ms, 3), "rc": rc, "iters": [s["iters"] for s in st],
+                     "true_rel_resid_max": max(s["true_rel_resid"] for s in st)}
+    ref = xs["cg_fp64"]
+    for name in ("fgmres_identity", "fgmres_ptc"):
+        res[name]["rel_err_vs_cg"] = float(np.linalg.norm(xs[name] - ref) / np.linalg.norm(ref))
+    res["ptc_iteration_gain_vs_fgmres"] = round(sum(res["fgmres_identity"]["iters"]) /
+                                                max(1, sum(res["fgmres_ptc"]["iters"])), 3)
+    res["ptc_time_vs_cg"] = round(res["cg_fp64"]["ms"] / res["fgmres_ptc"]["ms"], 3)
+    lat.close()
+    return res
+
+
+def bench_batch(synth, mfq, torch, dev, np):
+    """The 64-lattice uneven batch (8^4, 12^4, 16^3x32 SF; 1-8 RHS each;
+    kappa in [0.12, 0.135]) in one persistent launch per CG phase, FP32 inner
+    with FP64 reliable updates to 1e-10, against solving the lattices one by one."""
+    probs = synth.batch_problems()
+    print(f"[bench] row batch: generating {len(probs)} lattices", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    lats, bs = [], []
+    for q in probs:
+        lats.append(mfq.Lattice(q.dims, q.bc, q.kappa, torch.from_numpy(q.links()).to(dev)))
+        bs.append(torch.from_numpy(q.rhs()).to(dev))
+    gen_s = time.perf_counter() - t
+    batch = mfq.Batch(lats, [q.n_rhs for q in probs], prec="fp32")
+    pr = mfq.make_params(tol=1e-10, prec="fp32", max_iter=20000)
+    ms, (xs, stats, rc) = _timed(lambda: batch.solve(bs, params=pr), reps=2)
+    print(f"[bench] batch solve {ms:.1f} ms rc={rc}", file=sys.stderr, flush=True)
+    t_one = 0.0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for lat, b in zip(lats, bs):
+        lat.solve(b, params=pr)
+    torch.cuda.synchronize()
+    t_one = (time.perf_counter() - t) * 1e3
+    n_rhs = sum(q.n_rhs for q in probs)
+    site_rhs = sum(q.n_rhs * q.dims[0] * q.dims[1] * q.dims[2] * (q.dims[3] - 1) for q in probs)
+    iters = [s["iters"] for st in stats for s in st]
+    res = {"lattices": len(probs), "rhs": n_rhs, "grid": batch.grid, "ms": round(ms, 2), "rc": rc,
+           "one_by_one_ms": round(t_one, 2), "speedup_vs_one_by_one": round(t_one / ms, 3),
+           "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
+           "true_rel_resid_max": max(s["true_rel_resid"] for st in stats for s in st),
+           "site_rhs_iterations_per_s": round(sum(q.dims[0] * q.dims[1] * q.dims[2] * (q.dims[3] - 1)
+                                                  * s["iters"] for q, st in zip(probs, stats) for s in st)
+                                              / (ms * 1e-3), 1),
+           "site_rhs": site_rhs, "input_generation_s": round(gen_s, 2)}
+    batch.close()
+    for lat in lats:
+        lat.close()
+    return res
+
+
+def profile_kernels(args, synth, mfq, torch, dev):
+    """Counter run: the fused half-dslash of the inner CG on the bench lattice
+    (its tuned launch shape, 50 launches) and a plain 1 GiB device copy, whose
+    FETCH_SIZE / WRITE_SIZE calibrate the counters against known bytes."""
+    p = synth.CONFIG_1
+    lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
+    ms = lat.time_hop(args.prec, p.n_rhs, iters=50)
+    shape = lat.hop_shape(args.prec, p.n_rhs)
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_kernels": True, "hop_ms": ms, "shape": shape, "copy_bytes": src.numel() * 8}))
+    lat.close()
 
 
 if __name__ == "__main__":

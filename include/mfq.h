@@ -93,7 +93,13 @@ typedef enum {
   MFQ_OP_HOP_DAG = 6
 } mfq_op;
 
-typedef enum { MFQ_PC_NONE = 0, MFQ_PC_PTC = 1 } mfq_pc;
+/* Solver selection: NONE is CG on D^+D; PTC is restarted flexible GMRES
+ * (restart = mfq_solve_params.restart, FP64 Arnoldi) right-preconditioned by
+ * the learned parallel-transport network, with CG as the fallback when a
+ * cycle stagnates or breaks down (status MFQ_FELL_BACK); IDENTITY is the same
+ * GMRES without preconditioner (the reference the network is measured
+ * against). */
+typedef enum { MFQ_PC_NONE = 0, MFQ_PC_PTC = 1, MFQ_PC_IDENTITY = 2 } mfq_pc;
 
 typedef struct {
   int dims[4]; /* Lx, Ly, Lz, T: even, >= 2 (T >= 4 for SF)                  */
@@ -121,7 +127,11 @@ typedef struct {
 } mfq_solve_stats;
 
 /* Create a handle for one lattice and pack the links (canonical FP64 device
- * array, see above) into the internal FP64, FP32 and FP16 copies. */
+ * array, see above) into the internal FP64, FP32 and FP16 copies.  The FP32
+ * and FP16 copies store the first two rows of each link and rebuild the third
+ * (unit determinant); if any link is not SU(3) to 1e-10 the handle still
+ * works in FP64, while FP32/FP16 solves and the learned preconditioner
+ * return MFQ_ERR_ARG. */
 int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mfq_handle** out);
 
 /* Repack the links after they changed (for example after an MD step). */
@@ -150,6 +160,70 @@ int mfq_fermion_force(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq
                       double* force_dev, double* action_host, double* x_dev, double* y_dev,
                       mfq_solve_stats* stats_host, void* stream);
 
+/* ---- many lattices in one persistent launch per CG phase --------------
+ * A batch groups distinct handles (lattices of any size, each with its own
+ * links and kappa) with n_rhs[i] right-hand sides each (1..64).  Every CG
+ * phase of all lattices runs as one launch of a persistent kernel over a
+ * static list of (lattice, site tile, RHS group) tiles; the iterations are
+ * captured in a hipGraph.  Each lattice keeps its own per-RHS scalars and
+ * convergence; precision is fixed per batch (mfq_prec).  The batch uses the
+ * handles' workspaces: using a handle elsewhere with more RHS reallocates
+ * them, after which mfq_batch_solve returns MFQ_ERR_STATE (re-create it).
+ * Destroy the batch before its handles. */
+typedef struct mfq_batch mfq_batch;
+
+int mfq_batch_create(mfq_handle** hs, int n_lat, const int* n_rhs, int prec, void* stream, mfq_batch** out);
+
+/* b_dev[i], x_dev[i]: canonical spinors of lattice i (n_rhs[i] each).
+ * stats_host: sum of n_rhs records, lattice by lattice.  Host-blocking. */
+int mfq_batch_solve(mfq_batch* batch, const double* const* b_dev, double* const* x_dev,
+                    const mfq_solve_params* params, mfq_solve_stats* stats_host, void* stream);
+
+/* One-shot form: create, solve, destroy. */
+int mfq_solve_batch(mfq_handle** hs, int n_lat, const double* const* b_dev, double* const* x_dev,
+                    const int* n_rhs, const mfq_solve_params* params, mfq_solve_stats* stats_host,
+                    void* stream);
+
+/* Persistent grid size chosen by the batch's autotuning (workgroups). */
+int mfq_batch_grid(mfq_batch* batch);
+
+void mfq_batch_destroy(mfq_batch* batch);
+
+/* ---- learned preconditioner: gauge-covariant parallel-transport network --
+ * M = L2 L1 with L(psi)[c'](n) = sum_c sum_p W[p][c'][c] (T_p psi[c])(n) over
+ * the 9 paths p (identity; U_mu(n) psi(n+mu); U_mu(n-mu)^+ psi(n-mu)), W a
+ * complex 4x4 spin matrix, channels 1 -> 8 -> 1, linear.  Weights are
+ * 2 x 9 x 8 x 16 complex numbers, passed as interleaved FP64 re/im:
+ * W1[p][c'][s'][s] (layer 1), then W2[p][c][s'][s] (layer 2).  Training keeps
+ * FP32 master weights; inference uses their BF16-rounded values with FP32
+ * accumulation.  The network is trained on the GPU by this library's forward,
+ * backward and Adam kernels, on pairs (r_k, e_k) that CG generates.
+ * Pair arrays hold n_pairs canonical spinors (one RHS each). */
+
+/* Random initial weights (identity path near 1/sqrt(8) in both layers). */
+int mfq_precond_init(mfq_handle* h, unsigned long long seed, double scale);
+int mfq_precond_set_weights(mfq_handle* h, const double* w_host);
+/* which = 0: FP32 master weights, 1: BF16-rounded inference weights. */
+int mfq_precond_get_weights(mfq_handle* h, int which, double* w_host);
+/* out = M in for n_rhs canonical spinors (inference weights). */
+int mfq_precond_apply(mfq_handle* h, const double* in_dev, double* out_dev, int n_rhs, void* stream);
+/* loss = mean_k |M r_k - e_k|^2 / |e_k|^2 at the master weights and its
+ * gradient (dL/dRe W + i dL/dIm W, same layout as the weights). */
+int mfq_precond_loss_grad(mfq_handle* h, const double* r_dev, const double* e_dev, int n_pairs, double* loss_host,
+                          double* grad_host, void* stream);
+/* `steps` full-batch Adam steps (beta = 0.9, 0.999); loss before each step in
+ * loss_hist_host[steps] (may be NULL). */
+int mfq_precond_train(mfq_handle* h, const double* r_dev, const double* e_dev, int n_pairs, int steps, double lr,
+                      double* loss_hist_host, void* stream);
+/* Training pairs from plain FP64 CG on the n_rhs right-hand sides b: for
+ * j = 1..n_snap the iterate x_k after k = every * j iterations gives
+ * r = (b - A x_k) / |b - A x_k| and e = (x* - x_k) / |b - A x_k|, x* the
+ * converged solution.  r_out, e_out: n_snap * n_rhs spinors, pair j-major. */
+int mfq_precond_pairs(mfq_handle* h, const double* b_dev, int n_rhs, int every, int n_snap, double* r_out,
+                      double* e_out, void* stream);
+int mfq_precond_save(mfq_handle* h, const char* path);
+int mfq_precond_load(mfq_handle* h, const char* path);
+
 /* Thread-local message for the last negative status. */
 const char* mfq_last_error(void);
 
@@ -157,6 +231,18 @@ const char* mfq_last_error(void);
  * fused half-dslash of the inner CG at precision `prec` for n_rhs RHS), timed
  * with HIP events around `iters` back-to-back launches on `stream`. */
 int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, double* ms_out);
+
+/* Launch-shape autotuning of the inner solver's hopping kernel (on by
+ * default).  The first solve (or mfq_time_hop) for a given (n_rhs, precision)
+ * times candidate (sites per workgroup, RHS per workgroup, XCD remap) shapes
+ * with HIP events and keeps the fastest; MFQ_AUTOTUNE_CACHE, if set, names a
+ * text file where choices are stored and looked up.  Turning it off uses a
+ * fixed default shape.  Changing the setting drops tuned shapes and graphs. */
+int mfq_set_autotune(mfq_handle* h, int on);
+
+/* The shape the inner solver uses for (precision, n_rhs): shape3 receives
+ * {sites per workgroup, RHS per workgroup, XCD remap flag}. */
+int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape3);
 
 void mfq_destroy(mfq_handle* h);
 

@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import BC, OPS, PREC, MfqError, SolveStats, make_params
 
-__all__ = ["Lattice", "MfqError", "make_params", "BC", "OPS", "PREC"]
+__all__ = ["Lattice", "Batch", "MfqError", "make_params", "BC", "OPS", "PREC"]
 
 
 def spinor_shape(dims, bc, n_rhs):
@@ -105,9 +105,156 @@ class Lattice:
         out = (g, list(action), [s.as_dict() for s in stats], rc)
         return out + (x, y) if want_xy else out
 
+    def set_autotune(self, on: bool):
+        _lib.check(_lib.lib().mfq_set_autotune(self._h, int(bool(on))))
+
+    def hop_shape(self, prec: str, n_rhs: int):
+        """(sites per workgroup, RHS per workgroup, XCD remap) of the inner solver."""
+        out = (ctypes.c_int * 3)()
+        _lib.check(_lib.lib().mfq_hop_shape(self._h, PREC[prec], int(n_rhs), out))
+        return tuple(out)
+
     def time_hop(self, prec: str, n_rhs: int, iters: int = 50, stream=None) -> float:
         """Average ms of one launch of the inner solver's fused half-dslash."""
         ms = ctypes.c_double()
         _lib.check(_lib.lib().mfq_time_hop(self._h, PREC[prec], int(n_rhs), int(iters),
                                           _lib.stream_ptr(stream), ctypes.byref(ms)))
         return ms.value
+
+
+class Batch:
+    """Many lattices (each a ``Lattice`` with its own RHS count) solved together:
+    one persistent launch per CG phase for the whole batch."""
+
+    def __init__(self, lattices, n_rhs, prec: str = "fp32", stream=None):
+        self.lattices = list(lattices)
+        self.n_rhs = [int(n) for n in n_rhs]
+        self.prec = prec
+        n = len(self.lattices)
+        hs = (ctypes.c_void_p * n)(*[lat._h for lat in self.lattices])
+        nr = (ctypes.c_int * n)(*self.n_rhs)
+        b = ctypes.c_void_p()
+        _lib.check(_lib.lib().mfq_batch_create(hs, n, nr, PREC[prec], _lib.stream_ptr(stream), ctypes.byref(b)))
+        self._b = b
+
+    @property
+    def grid(self) -> int:
+        return _lib.lib().mfq_batch_grid(self._b)
+
+    def solve(self, bs, params=None, stream=None, **kw):
+        """bs: list of canonical spinor tensors; returns (xs, stats per lattice, status)."""
+        if len(bs) != len(self.lattices):
+            raise ValueError("one right-hand-side tensor per lattice")
+        p = params if params is not None else make_params(prec=self.prec, **kw)
+        for lat, b, n in zip(self.lattices, bs, self.n_rhs):
+            if lat._check_spinor(b) != n:
+                raise ValueError("RHS count differs from the batch's")
+        xs = [torch.empty_like(b) for b in bs]
+        n = len(bs)
+        bp = (ctypes.c_void_p * n)(*[_lib.dptr(b).value for b in bs])
+        xp = (ctypes.c_void_p * n)(*[_lib.dptr(x).value for x in xs])
+        stats = (SolveStats * sum(self.n_rhs))()
+        rc = _lib.lib().mfq_batch_solve(self._b, bp, xp, ctypes.byref(p), stats, _lib.stream_ptr(stream))
+        _lib.check(rc, allow=(0, 1))
+        flat = [s.as_dict() for s in stats]
+        out, k = [], 0
+        for nr in self.n_rhs:
+            out.append(flat[k:k + nr])
+            k += nr
+        return xs, out, rc
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib.lib().mfq_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- learned preconditioner
+N_PTC_COMPLEX = 2 * 9 * 8 * 16
+
+
+def _w_to_array(w):
+    import numpy as np
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1))
+    if w.size != N_PTC_COMPLEX:
+        raise ValueError(f"expected {N_PTC_COMPLEX} complex weights")
+    return w
+
+
+def _precond_init(self, seed: int = 0, scale: float = 0.1):
+    _lib.check(_lib.lib().mfq_precond_init(self._h, int(seed), float(scale)))
+
+
+def _precond_set_weights(self, w):
+    a = _w_to_array(w)
+    _lib.check(_lib.lib().mfq_precond_set_weights(self._h, ctypes.c_void_p(a.ctypes.data)))
+
+
+def _precond_get_weights(self, which: str = "master"):
+    import numpy as np
+    out = np.zeros(N_PTC_COMPLEX, dtype=np.complex128)
+    _lib.check(_lib.lib().mfq_precond_get_weights(self._h, 0 if which == "master" else 1,
+                                                  ctypes.c_void_p(out.ctypes.data)))
+    return out
+
+
+def _precond_apply(self, psi: torch.Tensor, stream=None) -> torch.Tensor:
+    n = self._check_spinor(psi)
+    out = torch.empty_like(psi)
+    _lib.check(_lib.lib().mfq_precond_apply(self._h, _lib.dptr(psi), _lib.dptr(out), n, _lib.stream_ptr(stream)))
+    return out
+
+
+def _precond_loss_grad(self, r: torch.Tensor, e: torch.Tensor, stream=None):
+    import numpy as np
+    n = self._check_spinor(r)
+    loss = ctypes.c_double()
+    grad = np.zeros(N_PTC_COMPLEX, dtype=np.complex128)
+    _lib.check(_lib.lib().mfq_precond_loss_grad(self._h, _lib.dptr(r), _lib.dptr(e), n, ctypes.byref(loss),
+                                                ctypes.c_void_p(grad.ctypes.data), _lib.stream_ptr(stream)))
+    return loss.value, grad
+
+
+def _precond_train(self, r: torch.Tensor, e: torch.Tensor, steps: int = 100, lr: float = 1e-3, stream=None):
+    import numpy as np
+    n = self._check_spinor(r)
+    hist = np.zeros(int(steps))
+    _lib.check(_lib.lib().mfq_precond_train(self._h, _lib.dptr(r), _lib.dptr(e), n, int(steps), float(lr),
+                                            ctypes.c_void_p(hist.ctypes.data), _lib.stream_ptr(stream)))
+    return hist
+
+
+def _precond_pairs(self, b: torch.Tensor, every: int, n_snap: int, stream=None):
+    """(r, e) training pairs from plain CG on b: n_snap * n_rhs spinors each."""
+    n = self._check_spinor(b)
+    shape = self.spinor_shape(n * n_snap)
+    r = torch.empty(shape, dtype=torch.complex128, device=b.device)
+    e = torch.empty(shape, dtype=torch.complex128, device=b.device)
+    _lib.check(_lib.lib().mfq_precond_pairs(self._h, _lib.dptr(b), n, int(every), int(n_snap), _lib.dptr(r),
+                                            _lib.dptr(e), _lib.stream_ptr(stream)))
+    return r, e
+
+
+def _precond_save(self, path: str):
+    _lib.check(_lib.lib().mfq_precond_save(self._h, str(path).encode()))
+
+
+def _precond_load(self, path: str):
+    _lib.check(_lib.lib().mfq_precond_load(self._h, str(path).encode()))
+
+
+Lattice.precond_init = _precond_init
+Lattice.precond_set_weights = _precond_set_weights
+Lattice.precond_get_weights = _precond_get_weights
+Lattice.precond_apply = _precond_apply
+Lattice.precond_loss_grad = _precond_loss_grad
+Lattice.precond_train = _precond_train
+Lattice.precond_pairs = _precond_pairs
+Lattice.precond_save = _precond_save
+Lattice.precond_load = _precond_load

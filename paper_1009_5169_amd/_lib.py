@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmfq.so")
 BC = {"sf": 0, "periodic": 1, "antiperiodic": 2}
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 OPS = {"hop_eo": 0, "hop_oe": 1, "D": 2, "Ddag": 3, "DdagD": 4, "hop": 5, "hop_dag": 6}
-PRECOND = {"none": 0, "ptc": 1}
+PRECOND = {"none": 0, "ptc": 1, "identity": 2}
 
 MFQ_OK, MFQ_NOT_CONVERGED, MFQ_FELL_BACK = 0, 1, 2
 
@@ -64,6 +64,26 @@ _SIGNATURES = {
                           ctypes.c_int),
     "mfq_time_hop": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
                       ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "mfq_set_autotune": ([_P, ctypes.c_int], ctypes.c_int),
+    "mfq_hop_shape": ([_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "mfq_batch_create": ([ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _P,
+                          ctypes.POINTER(_P)], ctypes.c_int),
+    "mfq_batch_solve": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(SolveParams),
+                         ctypes.POINTER(SolveStats), _P], ctypes.c_int),
+    "mfq_solve_batch": ([ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats),
+                         _P], ctypes.c_int),
+    "mfq_batch_grid": ([_P], ctypes.c_int),
+    "mfq_batch_destroy": ([_P], None),
+    "mfq_precond_init": ([_P, ctypes.c_ulonglong, ctypes.c_double], ctypes.c_int),
+    "mfq_precond_set_weights": ([_P, _P], ctypes.c_int),
+    "mfq_precond_get_weights": ([_P, ctypes.c_int, _P], ctypes.c_int),
+    "mfq_precond_apply": ([_P, _P, _P, ctypes.c_int, _P], ctypes.c_int),
+    "mfq_precond_loss_grad": ([_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P, _P], ctypes.c_int),
+    "mfq_precond_train": ([_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, _P], ctypes.c_int),
+    "mfq_precond_pairs": ([_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P], ctypes.c_int),
+    "mfq_precond_save": ([_P, ctypes.c_char_p], ctypes.c_int),
+    "mfq_precond_load": ([_P, ctypes.c_char_p], ctypes.c_int),
     "mfq_last_error": ([], ctypes.c_char_p),
     "mfq_destroy": ([_P], None),
 }

@@ -8,12 +8,11 @@
 #include <chrono>
 #include <string>
 
-#include "internal.h"
-#include "mfq.h"
+#include "handle.h"
 
 using namespace mfq;
 
-namespace {
+namespace mfq {
 thread_local std::string g_err;
 
 int fail(int code, const std::string& msg) {
@@ -26,11 +25,7 @@ int fail_hip(hipError_t e, const char* what) {
 }
 }  // namespace
 
-#define HIPCHK(...)                                          \
-  do {                                                       \
-    hipError_t e_ = (__VA_ARGS__);                           \
-    if (e_ != hipSuccess) return fail_hip(e_, #__VA_ARGS__); \
-  } while (0)
+
 
 namespace mfq {
 hipError_t ensure(DevBuf& b, size_t bytes) {
@@ -50,38 +45,7 @@ void release(DevBuf& b) {
 }
 }  // namespace mfq
 
-struct Workspace {
-  OwnedField<double> b64, x64, r64, t64, y64;
-  OwnedField<double> xd, rd, pd, td;
-  OwnedField<float> xs, rs, ps, ts;
-  OwnedField<_Float16> rh, ph, th;
-  DevBuf part, sc, sums, bad;
-  int cap_part = 0;  // RHS capacity of the partial-sum slots
-  int nblk_max = 0;
-  CgScalars* host_sc = nullptr;
-  int host_cap = 0;
-};
-
-// A captured run of k inner CG iterations.  The key holds everything the
-// captured kernel arguments depend on, so a stale graph never matches.
-struct GraphEntry {
-  std::vector<uintptr_t> key;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
-
-struct mfq_handle {
-  mfq_lattice lat;
-  Geom g;
-  int n_slices;
-  DevBuf links64, links32, links16;
-  Workspace ws;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipStream_t cap_stream = nullptr;  // used only to capture graphs
-  std::vector<GraphEntry> graphs;
-};
-
-namespace {
+namespace mfq {
 uintptr_t bits(double v) {
   uint64_t u;
   memcpy(&u, &v, sizeof(u));
@@ -94,13 +58,17 @@ void drop_graphs(mfq_handle* h) {
   }
   h->graphs.clear();
 }
-}  // namespace
 
-namespace {
+Links<double> links_d(mfq_handle* h) { return Links<double>{(const d2*)h->links64.ptr, h->g.vh, 0}; }
+Links<float> links_f(mfq_handle* h) { return Links<float>{(const f2*)h->links32.ptr, h->g.vh, 1}; }
+Links<_Float16> links_h(mfq_handle* h) { return Links<_Float16>{(const h2*)h->links16.ptr, h->g.vh, 1}; }
 
-Links<double> links_d(mfq_handle* h) { return Links<double>{(const d2*)h->links64.ptr, h->g.vh}; }
-Links<float> links_f(mfq_handle* h) { return Links<float>{(const f2*)h->links32.ptr, h->g.vh}; }
-Links<_Float16> links_h(mfq_handle* h) { return Links<_Float16>{(const h2*)h->links16.ptr, h->g.vh}; }
+int need_su3(mfq_handle* h, int prec, int precond) {
+  if ((prec != MFQ_PREC_FP64 || precond == MFQ_PC_PTC) && !h->links_su3)
+    return fail(MFQ_ERR_ARG, "FP32/FP16 precision and the learned preconditioner need SU(3) links "
+                             "(unitary, det 1 to 1e-10); use FP64");
+  return MFQ_OK;
+}
 
 int check_lattice(const mfq_lattice* lat) {
   if (!lat) return fail(MFQ_ERR_ARG, "lattice is NULL");
@@ -153,16 +121,6 @@ int pack_checked(mfq_handle* h, const double* canon, int n_rhs, int gamma5, hipS
 }
 
 // ------------------------------------------------- operator application
-template <typename S, typename SX>
-HopArgs<S, SX> hop_args(mfq_handle* h, Links<S> L, int n_rhs) {
-  HopArgs<S, SX> a;
-  memset((void*)&a, 0, sizeof(a));
-  a.g = h->g;
-  a.links = L;
-  a.n_rhs = n_rhs;
-  a.skip_state = 3;
-  return a;
-}
 
 // out = op(in) in storage S; tmp is scratch (DDAGD only).  Fields are views.
 template <typename S>
@@ -216,6 +174,92 @@ int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field
   }
 }
 
+// ------------------------------------------------------------- autotuner
+// Launch-shape autotuning of the inner hopping kernel: (sites per workgroup,
+// RHS per workgroup, XCD remap) candidates are timed with HIP events on the
+// fields the solve will use; the fastest is kept per (n_rhs, precision) for
+// the life of the handle and, if MFQ_AUTOTUNE_CACHE names a file, appended
+// there keyed by (arch, dims, bc, n_rhs, precision).
+std::string tune_key(mfq_handle* h, int n, int prec) {
+  char buf[160];
+  snprintf(buf, sizeof(buf), "gfx950 %d %d %d %d %d %d %d", h->lat.dims[0], h->lat.dims[1], h->lat.dims[2],
+           h->lat.dims[3], h->lat.bc, n, prec);
+  return buf;
+}
+
+bool tune_cache_lookup(mfq_handle* h, int n, int prec, Shape* out) {
+  for (auto& e : h->tuned)
+    if (e.n == n && e.prec == prec) {
+      *out = e.sh;
+      return true;
+    }
+  const char* path = getenv("MFQ_AUTOTUNE_CACHE");
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  const std::string key = tune_key(h, n, prec);
+  char line[256];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    int sb, nr, xcd;
+    const char* bar = strchr(line, '|');
+    if (!bar || std::string(line, bar - line) != key) continue;
+    if (sscanf(bar + 1, "%d %d %d", &sb, &nr, &xcd) == 3 && sb >= 64 && sb % 64 == 0 && nr >= 1 &&
+        sb * nr <= 512) {
+      out->sb = sb;
+      out->nr = nr;
+      out->xcd = xcd;
+      found = true;
+    }
+  }
+  fclose(f);
+  if (found) h->tuned.push_back({n, prec, *out, 0.f});
+  return found;
+}
+
+template <typename S, typename SX>
+int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<S> dst, hipStream_t st,
+                Shape* out) {
+  *out = default_shape(n);
+  if (!h->autotune || tune_cache_lookup(h, n, prec, out)) return MFQ_OK;
+  HopArgs<S, SX> a = hop_args<S, SX>(h, L, n);
+  a.in = a.self = src;
+  a.out = dst;
+  a.coef = -h->lat.kappa;
+  a.part = part_slot(h, 3);
+  float best = 1e30f;
+  Shape best_sh = *out;
+  const int nrs[4] = {1, 2, 4, n < 8 ? n : 8};
+  for (int sb = 64; sb <= 256; sb *= 2)
+    for (int k = 0; k < 4; ++k) {
+      const int nr = nrs[k];
+      if (nr > n || sb * nr > 512 || (k > 0 && nr == nrs[k - 1])) continue;
+      for (int xcd = 0; xcd < 2; ++xcd) {
+        Shape sh{sb, nr, xcd};
+        for (int i = 0; i < 2; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+        HIPCHK(hipEventRecord(h->ev0, st));
+        for (int i = 0; i < 10; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+        HIPCHK(hipEventRecord(h->ev1, st));
+        HIPCHK(hipEventSynchronize(h->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        if (ms < best * 0.97f) {  // prefer earlier (simpler) shapes on near ties
+          best = ms;
+          best_sh = sh;
+        }
+      }
+    }
+  *out = best_sh;
+  h->tuned.push_back({n, prec, best_sh, best * 100.f});
+  if (const char* path = getenv("MFQ_AUTOTUNE_CACHE")) {
+    if (FILE* f = fopen(path, "a")) {
+      fprintf(f, "%s|%d %d %d\n", tune_key(h, n, prec).c_str(), best_sh.sb, best_sh.nr, best_sh.xcd);
+      fclose(f);
+    }
+  }
+  return MFQ_OK;
+}
+
 // ------------------------------------------------------------- CG driver
 template <typename S, typename SX>
 struct InnerFields {
@@ -236,7 +280,9 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
            double delta, hipStream_t st, mfq_solve_stats* stats) {
   Workspace& w = h->ws;
   const Geom& g = h->g;
-  const Shape sh = default_shape(n);
+  Shape sh;
+  int rc0 = tuned_shape<S, SX>(h, n, (int)sizeof(S), in.L, in.p, in.t, st, &sh);
+  if (rc0 != MFQ_OK) return rc0;
   const double mk = -h->lat.kappa;
   const double tol2 = P->tol * P->tol;
   const double delta2 = delta * delta;
@@ -334,7 +380,8 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     std::vector<uintptr_t> key = {(uintptr_t)sizeof(S), (uintptr_t)sizeof(SX), (uintptr_t)n, (uintptr_t)k,
                                   (uintptr_t)in.r.data, (uintptr_t)in.p.data, (uintptr_t)in.t.data,
                                   (uintptr_t)in.x.data, (uintptr_t)in.L.data, (uintptr_t)w.part.ptr,
-                                  (uintptr_t)sc, bits(tol2), bits(delta2)};
+                                  (uintptr_t)sc, bits(tol2), bits(delta2), (uintptr_t)sh.sb,
+                                  (uintptr_t)sh.nr, (uintptr_t)sh.xcd};
     GraphEntry* hit = nullptr;
     for (auto& e : h->graphs)
       if (e.key == key) hit = &e;
@@ -427,12 +474,15 @@ int check_params(const mfq_solve_params* P) {
   if (!(P->tol > 0.0) || P->tol >= 1.0) return fail(MFQ_ERR_ARG, "tol must be in (0, 1)");
   if (P->max_iter < 1) return fail(MFQ_ERR_ARG, "max_iter must be >= 1");
   if (P->prec < MFQ_PREC_FP64 || P->prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
-  if (P->precond != MFQ_PC_NONE) return fail(MFQ_ERR_ARG, "preconditioner not available in this call");
+  if (P->precond < MFQ_PC_NONE || P->precond > MFQ_PC_IDENTITY) return fail(MFQ_ERR_ARG, "unknown preconditioner");
+  if (P->restart > 32) return fail(MFQ_ERR_ARG, "restart must be <= 32");
   return MFQ_OK;
 }
 
 // Solve D^+D x64 = b64 for n RHS at the requested precision.
 int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
+  if (int rc = need_su3(h, P->prec, P->precond)) return rc;
+  if (P->precond == MFQ_PC_PTC || P->precond == MFQ_PC_IDENTITY) return run_fgmres(h, n, P, st, stats);
   Workspace& w = h->ws;
   const Geom& g = h->g;
   const double delta = P->reliable_delta > 0.0 ? P->reliable_delta : 0.1;
@@ -479,17 +529,21 @@ int pack_all_links(mfq_handle* h, const double* links_dev, hipStream_t st) {
   Workspace& w = h->ws;
   HIPCHK(ensure(w.bad, sizeof(int)));
   HIPCHK(hipMemsetAsync(w.bad.ptr, 0, sizeof(int), st));
-  HIPCHK(launch_pack_links<double>(h->g, links_dev, (d2*)h->links64.ptr, (int*)w.bad.ptr, st));
-  HIPCHK(launch_pack_links<float>(h->g, links_dev, (f2*)h->links32.ptr, nullptr, st));
-  HIPCHK(launch_pack_links<_Float16>(h->g, links_dev, (h2*)h->links16.ptr, nullptr, st));
+  HIPCHK(launch_pack_links<double>(h->g, links_dev, (d2*)h->links64.ptr, (int*)w.bad.ptr, 0, 1, st));
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, w.bad.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (bad) return fail(MFQ_ERR_ARG, "links hold NaN or Inf");
+  if (bad & 1) return fail(MFQ_ERR_ARG, "links hold NaN or Inf");
+  // the FP32 / FP16 inner-solver copies store two rows per link and rebuild
+  // the third, which needs SU(3) links; other links allow FP64 only
+  h->links_su3 = (bad & 2) ? 0 : 1;
+  drop_graphs(h);
+  HIPCHK(launch_pack_links<float>(h->g, links_dev, (f2*)h->links32.ptr, nullptr, 1, 0, st));
+  HIPCHK(launch_pack_links<_Float16>(h->g, links_dev, (h2*)h->links16.ptr, nullptr, 1, 0, st));
   return MFQ_OK;
 }
 
-}  // namespace
+}  // namespace mfq
 
 extern "C" {
 
@@ -547,8 +601,9 @@ int mfq_dslash_prec(mfq_handle* h, int op, int prec, const double* in_dev, doubl
   if (op < MFQ_OP_HOP_EO || op > MFQ_OP_HOP_DAG) return fail(MFQ_ERR_ARG, "unknown operator");
   if (prec < MFQ_PREC_FP64 || prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
   hipStream_t st = (hipStream_t)stream;
-  int rc = ensure_fp64_fields(h, n_rhs);
+  int rc = need_su3(h, prec, MFQ_PC_NONE);
   if (rc) return rc;
+  if ((rc = ensure_fp64_fields(h, n_rhs))) return rc;
   Workspace& w = h->ws;
   const Geom& g = h->g;
   const Shape sh = default_shape(n_rhs);
@@ -648,12 +703,14 @@ int mfq_fermion_force(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq
 int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, double* ms_out) {
   if (!h || !ms_out) return fail(MFQ_ERR_ARG, "NULL argument");
   if (n_rhs < 1 || iters < 1) return fail(MFQ_ERR_ARG, "n_rhs and iters must be >= 1");
+  if (prec < MFQ_PREC_FP64 || prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
   hipStream_t st = (hipStream_t)stream;
   int rc = ensure_fp64_fields(h, n_rhs);
   if (rc) return rc;
   Workspace& w = h->ws;
   const Geom& g = h->g;
-  const Shape sh = default_shape(n_rhs);
+  const Shape sh0 = default_shape(n_rhs);
+  // time the kernel the inner CG launches: same fields, same tuned shape
   auto timed = [&](auto launch) -> int {
     for (int i = 0; i < 3; ++i) HIPCHK(launch());
     HIPCHK(hipEventRecord(h->ev0, st));
@@ -666,34 +723,66 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
     return MFQ_OK;
   };
   HIPCHK(hipMemsetAsync(w.b64.data.ptr, 0, field_chunks<double>(g, n_rhs) * sizeof(d2), st));
+  Shape sh;
   if (prec == MFQ_PREC_FP64) {
+    HIPCHK(w.pd.alloc(g, n_rhs));
+    HIPCHK(w.td.alloc(g, n_rhs));
+    HIPCHK(launch_convert<double, double>(g, w.b64.view(g), w.pd.view(g), 0, n_rhs, sh0, st));
+    if ((rc = tuned_shape<double, double>(h, n_rhs, 8, links_d(h), w.pd.view(g), w.td.view(g), st, &sh))) return rc;
     HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n_rhs);
-    a.in = a.self = w.b64.view(g);
-    a.out = w.r64.view(g);
+    a.in = a.self = w.pd.view(g);
+    a.out = w.td.view(g);
     a.coef = -h->lat.kappa;
     a.part = part_slot(h, 0);
     return timed([&]() { return launch_hop<double, double>(EPI_D, a, sh, st); });
   } else if (prec == MFQ_PREC_FP32_RELIABLE) {
-    HIPCHK(w.rs.alloc(g, n_rhs));
+    HIPCHK(w.ps.alloc(g, n_rhs));
     HIPCHK(w.ts.alloc(g, n_rhs));
-    HIPCHK(launch_convert<double, float>(g, w.b64.view(g), w.rs.view(g), 0, n_rhs, sh, st));
+    HIPCHK(launch_convert<double, float>(g, w.b64.view(g), w.ps.view(g), 0, n_rhs, sh0, st));
+    if ((rc = tuned_shape<float, float>(h, n_rhs, 4, links_f(h), w.ps.view(g), w.ts.view(g), st, &sh))) return rc;
     HopArgs<float, float> a = hop_args<float, float>(h, links_f(h), n_rhs);
-    a.in = a.self = w.rs.view(g);
+    a.in = a.self = w.ps.view(g);
     a.out = w.ts.view(g);
     a.coef = -h->lat.kappa;
     a.part = part_slot(h, 0);
     return timed([&]() { return launch_hop<float, float>(EPI_D, a, sh, st); });
   } else {
-    HIPCHK(w.rh.alloc(g, n_rhs));
+    HIPCHK(w.ph.alloc(g, n_rhs));
     HIPCHK(w.th.alloc(g, n_rhs));
-    HIPCHK(launch_convert<double, _Float16>(g, w.b64.view(g), w.rh.view(g), 0, n_rhs, sh, st));
+    HIPCHK(launch_convert<double, _Float16>(g, w.b64.view(g), w.ph.view(g), 0, n_rhs, sh0, st));
+    if ((rc = tuned_shape<_Float16, float>(h, n_rhs, 2, links_h(h), w.ph.view(g), w.th.view(g), st, &sh)))
+      return rc;
     HopArgs<_Float16, float> a = hop_args<_Float16, float>(h, links_h(h), n_rhs);
-    a.in = a.self = w.rh.view(g);
+    a.in = a.self = w.ph.view(g);
     a.out = w.th.view(g);
     a.coef = -h->lat.kappa;
     a.part = part_slot(h, 0);
     return timed([&]() { return launch_hop<_Float16, float>(EPI_D, a, sh, st); });
   }
+}
+
+int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape3) {
+  if (!h || !shape3) return fail(MFQ_ERR_ARG, "NULL argument");
+  for (auto& e : h->tuned)
+    if (e.n == n_rhs && e.prec == (prec == 0 ? 8 : prec == 1 ? 4 : 2)) {
+      shape3[0] = e.sh.sb;
+      shape3[1] = e.sh.nr;
+      shape3[2] = e.sh.xcd;
+      return MFQ_OK;
+    }
+  const Shape sh = default_shape(n_rhs);
+  shape3[0] = sh.sb;
+  shape3[1] = sh.nr;
+  shape3[2] = sh.xcd;
+  return MFQ_OK;
+}
+
+int mfq_set_autotune(mfq_handle* h, int on) {
+  if (!h) return fail(MFQ_ERR_ARG, "NULL handle");
+  h->autotune = on ? 1 : 0;
+  h->tuned.clear();
+  drop_graphs(h);
+  return MFQ_OK;
 }
 
 void mfq_destroy(mfq_handle* h) {

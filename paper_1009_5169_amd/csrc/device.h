@@ -12,8 +12,8 @@
 //       FP16:  3 chunks of four complex (8 x fp16), plus a norm array
 //              [rhs][parity][site] (fp32): stored value = value / norm,
 //              norm = max |real component| of the 24 reals of the site.
-//   link array          [parity][mu][9][site]  (FP64 double2, FP32 float2,
-//                                               FP16 2 x fp16 per complex)
+//   link array          FP64 [parity][mu][9][site] (double2); FP32 / FP16
+//                       [parity][mu][3][site] chunks of the first two rows
 //
 // A "site" is a half-lattice index s = xh + (Lx/2)(y + Ly(z + Lz t)) over the
 // dynamical time slices t = 0..Td-1 (x0 = t + 1 under Schroedinger-functional
@@ -29,6 +29,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------- complex
@@ -129,14 +130,34 @@ struct Field {
   }
 };
 
+// Links of one precision.  FP64: full layout [parity][mu][9][site], one
+// complex per element.  FP32 and FP16 (the inner-solver copies, SU(3) links
+// only): the first two rows, [parity][mu][3][site] of 16-byte (FP32) or
+// 8-byte (FP16) chunks of two complex numbers; the third row is rebuilt as the
+// complex conjugate of the cross product of the first two, so a link costs
+// 48 (FP32) or 24 (FP16) bytes and three loads.
 template <typename S>
 struct Links {
-  const typename Store<S>::link_elem* data;  // [parity][mu][9][vh]
+  const typename Store<S>::link_elem* data;  // [parity][mu][9][vh] (full layout)
   int vh;
+  int comp;  // 1 for the two-row layout (FP32 / FP16)
   __device__ __forceinline__ long idx(int par, int mu, int k, int s) const {
     return ((long)(par * 4 + mu) * 9 + k) * vh + s;
   }
+  __device__ __forceinline__ long cidx(int par, int mu, int c, int s) const {
+    return ((long)(par * 4 + mu) * 3 + c) * vh + s;
+  }
 };
+
+template <typename T>
+__device__ __forceinline__ void third_row(cpx<T> u[9]) {
+  u[6] = {u[1].re * u[5].re - u[1].im * u[5].im - (u[2].re * u[4].re - u[2].im * u[4].im),
+          -(u[1].re * u[5].im + u[1].im * u[5].re - (u[2].re * u[4].im + u[2].im * u[4].re))};
+  u[7] = {u[2].re * u[3].re - u[2].im * u[3].im - (u[0].re * u[5].re - u[0].im * u[5].im),
+          -(u[2].re * u[3].im + u[2].im * u[3].re - (u[0].re * u[5].im + u[0].im * u[5].re))};
+  u[8] = {u[0].re * u[4].re - u[0].im * u[4].im - (u[1].re * u[3].re - u[1].im * u[3].im),
+          -(u[0].re * u[4].im + u[0].im * u[4].re - (u[1].re * u[3].im + u[1].im * u[3].re))};
+}
 
 // Spinor register block: v[3 * spin + colour].
 template <typename T>
@@ -223,18 +244,28 @@ __device__ __forceinline__ void load_link(const Links<double>& l, int par, int m
 }
 template <typename T>
 __device__ __forceinline__ void load_link(const Links<float>& l, int par, int mu, int s, cpx<T> u[9]) {
+  {
+    const f4* c = (const f4*)l.data;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    f2 q = l.data[l.idx(par, mu, k, s)];
-    u[k] = {(T)q.x, (T)q.y};
+    for (int k = 0; k < 3; ++k) {
+      f4 q = c[l.cidx(par, mu, k, s)];
+      u[2 * k] = {(T)q.x, (T)q.y};
+      u[2 * k + 1] = {(T)q.z, (T)q.w};
+    }
+    third_row(u);
   }
 }
 template <typename T>
 __device__ __forceinline__ void load_link(const Links<_Float16>& l, int par, int mu, int s, cpx<T> u[9]) {
+  {
+    const h4* c = (const h4*)l.data;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    h2 q = l.data[l.idx(par, mu, k, s)];
-    u[k] = {(T)(float)q.x, (T)(float)q.y};
+    for (int k = 0; k < 3; ++k) {
+      h4 q = c[l.cidx(par, mu, k, s)];
+      u[2 * k] = {(T)(float)q.x, (T)(float)q.y};
+      u[2 * k + 1] = {(T)(float)q.z, (T)(float)q.w};
+    }
+    third_row(u);
   }
 }
 

@@ -1,0 +1,510 @@
+// Restarted flexible GMRES (right preconditioning) for all RHS at once, with
+// the learned PTC network as the preconditioner and plain CG as the fallback.
+//
+// Per RHS, a cycle of at most m steps builds an orthonormal basis v_j, the
+// preconditioned directions z_j = M v_j and the Hessenberg matrix H of
+// A z_j = sum_i H_ij v_i (classical Gram-Schmidt applied twice, FP64 dot
+// products), rotates H to triangular form with complex Givens rotations on
+// the device, and updates x += Z y with H y = g at the end of the cycle.  The
+// next cycle restarts from the FP64 true residual.  The host syncs once per
+// cycle.  If a cycle fails to reduce the true residual, or produces NaN, the
+// solve falls back to CG on the remaining residual.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "handle.h"
+#include "hop_impl.h"
+
+namespace mfq {
+
+constexpr int GM_MAXM = 32;
+
+struct GmState {
+  double hr[(GM_MAXM + 1) * GM_MAXM], hi[(GM_MAXM + 1) * GM_MAXM];  // H(i, j) at j * (M + 1) + i
+  double csr[GM_MAXM], csi[GM_MAXM], snr[GM_MAXM], sni[GM_MAXM];
+  double gr[GM_MAXM + 1], gi[GM_MAXM + 1];
+  double yr[GM_MAXM], yi[GM_MAXM];
+  double cr[GM_MAXM + 1], ci[GM_MAXM + 1];  // Gram-Schmidt coefficients of the current pass
+  double bnorm2, rtrue2, wnorm;
+  int k, active, done, iters, cycles, pad;
+};
+
+#define GM_LANE                                                    \
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;             \
+  const int r = blockIdx.y;                                        \
+  const bool valid = q < 2 * g.vh;                                 \
+  const int par = q >= g.vh ? 1 : 0;                               \
+  const int s = q - par * g.vh;
+
+__device__ __forceinline__ void block_sum2(double a, double b, double* part_a, double* part_b) {
+  __shared__ double ws[2][4];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    ws[0][threadIdx.x >> 6] = a;
+    ws[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *part_a = ((ws[0][0] + ws[0][1]) + ws[0][2]) + ws[0][3];
+    *part_b = ((ws[1][0] + ws[1][1]) + ws[1][2]) + ws[1][3];
+  }
+  __syncthreads();
+}
+
+// <v_l, w> for l < nv: partials part[((r * nv + l) * nblk + blk) * 2 + {re, im}]
+__global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> V, size_t vstride, int nv,
+                                                          Field<double> w, int n_rhs, double* part) {
+  GM_LANE
+  Spinor<double> ww;
+  if (valid) load_spinor(w, r, par, s, ww);
+  const int nblk = gridDim.x;
+  for (int l = 0; l < nv; ++l) {
+    double re = 0.0, im = 0.0;
+    if (valid) {
+      Field<double> vl = V;
+      vl.data += l * vstride;
+      Spinor<double> vv;
+      load_spinor(vl, r, par, s, vv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const cpx<double> d = cjmul(vv.v[k], ww.v[k]);
+        re += d.re;
+        im += d.im;
+      }
+    }
+    double* base = part + (((long)r * nv + l) * nblk + blockIdx.x) * 2;
+    block_sum2(re, im, base, base + 1);
+  }
+}
+
+// coefficients c_l = sum of partials; H(:, j) += c (accumulate over passes)
+__global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int n_rhs, GmState* st, int j, int first) {
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= n_rhs * nv) return;
+  const int r = w / nv, l = w % nv;
+  double re = 0.0, im = 0.0;
+  const double* p = part + ((long)r * nv + l) * nblk * 2;
+  for (int b = lane; b < nblk; b += 64) {
+    re += p[2 * b];
+    im += p[2 * b + 1];
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) {
+    GmState& S = st[r];
+    S.cr[l] = re;
+    S.ci[l] = im;
+    const int idx = j * (GM_MAXM + 1) + l;
+    if (first) {
+      S.hr[idx] = re;
+      S.hi[idx] = im;
+    } else {
+      S.hr[idx] += re;
+      S.hi[idx] += im;
+    }
+  }
+}
+
+// w -= sum_l c_l v_l
+__global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double> V, size_t vstride, int nv,
+                                                           Field<double> w, int n_rhs, const GmState* st) {
+  GM_LANE
+  if (!valid) return;
+  Spinor<double> ww;
+  load_spinor(w, r, par, s, ww);
+  for (int l = 0; l < nv; ++l) {
+    const cpx<double> c = {st[r].cr[l], st[r].ci[l]};
+    Field<double> vl = V;
+    vl.data += l * vstride;
+    Spinor<double> vv;
+    load_spinor(vl, r, par, s, vv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ww.v[k] = ww.v[k] - cmul(c, vv.v[k]);
+  }
+  store_spinor(w, r, par, s, ww);
+}
+
+__global__ __launch_bounds__(256) void gm_norm_kernel(Geom g, Field<double> w, int n_rhs, double* part) {
+  GM_LANE
+  double v = 0.0;
+  if (valid) {
+    Spinor<double> ww;
+    load_spinor(w, r, par, s, ww);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v += norm2(ww.v[k]);
+  }
+  double* base = part + ((long)r * gridDim.x + blockIdx.x) * 2;
+  block_sum2(v, 0.0, base, base + 1);
+}
+
+// which = 0: |w| -> H(j+1, j) and S.wnorm; which = 1: |b|^2 -> S.bnorm2,
+// beta = |b|, g = (beta, 0, ...); which = 2: true residual |r|^2 -> rtrue2,
+// done flag, restart g = (|r|, 0, ...)
+__global__ void gm_norm_finish_kernel(const double* part, int nblk, int n_rhs, GmState* st, int j, int which,
+                                      double tol2) {
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= n_rhs) return;
+  double v = 0.0;
+  const double* p = part + (long)w * nblk * 2;
+  for (int b = lane; b < nblk; b += 64) v += p[2 * b];
+  v = wave_sum(v);
+  if (lane != 0) return;
+  GmState& S = st[w];
+  if (which == 0) {
+    S.wnorm = sqrt(v);
+    S.hr[j * (GM_MAXM + 1) + j + 1] = S.wnorm;
+    S.hi[j * (GM_MAXM + 1) + j + 1] = 0.0;
+  } else {
+    if (which == 1) {
+      S.bnorm2 = v;
+      S.iters = 0;
+      S.cycles = 0;
+      S.done = v > 0.0 ? 0 : 1;
+    } else {
+      S.cycles += 1;
+      if (!S.done && v <= tol2 * S.bnorm2) S.done = 1;
+    }
+    S.rtrue2 = v;
+    S.wnorm = sqrt(v);
+    for (int i = 0; i <= GM_MAXM; ++i) S.gr[i] = S.gi[i] = 0.0;
+    S.gr[0] = S.wnorm;
+    S.k = 0;
+    S.active = S.done ? 0 : 1;
+  }
+}
+
+// v_out = w / |w| (|w| from the state); zero if |w| = 0
+__global__ __launch_bounds__(256) void gm_scale_kernel(Geom g, Field<double> w, Field<double> vout, int n_rhs,
+                                                       const GmState* st) {
+  GM_LANE
+  if (!valid) return;
+  const double nrm = st[r].wnorm;
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  Spinor<double> ww;
+  load_spinor(w, r, par, s, ww);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) ww.v[k] = inv * ww.v[k];
+  store_spinor(vout, r, par, s, ww);
+}
+
+// rotations for column j, one thread per RHS
+__global__ void gm_givens_kernel(GmState* st, int n_rhs, int j, int m, double tol2) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rhs) return;
+  GmState& S = st[r];
+  if (!S.active) return;
+  const int col = j * (GM_MAXM + 1);
+  for (int l = 0; l < j; ++l) {
+    const cpx<double> c = {S.csr[l], S.csi[l]}, sn = {S.snr[l], S.sni[l]};
+    const cpx<double> a = {S.hr[col + l], S.hi[col + l]}, b = {S.hr[col + l + 1], S.hi[col + l + 1]};
+    const cpx<double> t = cjmul(c, a) + cjmul(sn, b);
+    const cpx<double> u = cmul(c, b) - cmul(sn, a);
+    S.hr[col + l] = t.re;
+    S.hi[col + l] = t.im;
+    S.hr[col + l + 1] = u.re;
+    S.hi[col + l + 1] = u.im;
+  }
+  const cpx<double> a = {S.hr[col + j], S.hi[col + j]}, b = {S.hr[col + j + 1], S.hi[col + j + 1]};
+  const double den = sqrt(norm2(a) + norm2(b));
+  S.iters += 1;
+  if (!(den > 0.0) || !isfinite(den)) {  // breakdown: stop this cycle before column j
+    S.active = 0;
+    return;
+  }
+  const cpx<double> c = {a.re / den, a.im / den}, sn = {b.re / den, b.im / den};
+  S.csr[j] = c.re;
+  S.csi[j] = c.im;
+  S.snr[j] = sn.re;
+  S.sni[j] = sn.im;
+  S.hr[col + j] = den;
+  S.hi[col + j] = 0.0;
+  S.hr[col + j + 1] = 0.0;
+  S.hi[col + j + 1] = 0.0;
+  const cpx<double> gj = {S.gr[j], S.gi[j]};
+  const cpx<double> g1 = -cmul(sn, gj);
+  const cpx<double> g0 = cjmul(c, gj);
+  S.gr[j] = g0.re;
+  S.gi[j] = g0.im;
+  S.gr[j + 1] = g1.re;
+  S.gi[j + 1] = g1.im;
+  S.k = j + 1;
+  if (norm2(g1) <= tol2 * S.bnorm2 || j + 1 >= m) S.active = 0;
+}
+
+// back substitution H(0:k, 0:k) y = g(0:k), one thread per RHS
+__global__ void gm_solve_kernel(GmState* st, int n_rhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rhs) return;
+  GmState& S = st[r];
+  for (int i = S.k - 1; i >= 0; --i) {
+    cpx<double> acc = {S.gr[i], S.gi[i]};
+    for (int l = i + 1; l < S.k; ++l) {
+      const cpx<double> h = {S.hr[l * (GM_MAXM + 1) + i], S.hi[l * (GM_MAXM + 1) + i]};
+      acc = acc - cmul(h, cpx<double>{S.yr[l], S.yi[l]});
+    }
+    const double d = S.hr[i * (GM_MAXM + 1) + i];  // real after rotation
+    S.yr[i] = acc.re / d;
+    S.yi[i] = acc.im / d;
+  }
+}
+
+// x += sum_{j < k} y_j z_j
+__global__ __launch_bounds__(256) void gm_xupdate_kernel(Geom g, Field<double> Z, size_t zstride, Field<double> x,
+                                                         int n_rhs, const GmState* st) {
+  GM_LANE
+  if (!valid) return;
+  const int k = st[r].k;
+  if (k == 0) return;
+  Spinor<double> xx;
+  load_spinor(x, r, par, s, xx);
+  for (int j = 0; j < k; ++j) {
+    const cpx<double> y = {st[r].yr[j], st[r].yi[j]};
+    Field<double> zj = Z;
+    zj.data += j * zstride;
+    Spinor<double> zz;
+    load_spinor(zj, r, par, s, zz);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xx.v[c] = xx.v[c] + cmul(y, zz.v[c]);
+  }
+  store_spinor(x, r, par, s, xx);
+}
+
+// a += b (both parities, all RHS)
+__global__ __launch_bounds__(256) void gm_add_kernel(Geom g, Field<double> a, Field<double> b, int n_rhs) {
+  GM_LANE
+  if (!valid) return;
+  Spinor<double> x, y;
+  load_spinor(a, r, par, s, x);
+  load_spinor(b, r, par, s, y);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) x.v[k] = x.v[k] + y.v[k];
+  store_spinor(a, r, par, s, x);
+}
+
+}  // namespace mfq
+
+using namespace mfq;
+
+namespace {
+
+struct GmBufs {
+  OwnedField<double> V, Z, w, xsave;
+  DevBuf st, part;
+};
+
+struct GmCtx {
+  mfq_handle* h;
+  int n, m, use_pc;
+  GmBufs b;
+  GmState* host = nullptr;
+};
+
+}  // namespace
+
+namespace mfq {
+
+// Right-preconditioned FGMRES(m) on D^+D x64 = b64 (packed FP64).
+int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
+  const Geom& g = h->g;
+  Workspace& w = h->ws;
+  const int m = P->restart > 0 ? (P->restart < GM_MAXM ? P->restart : GM_MAXM) : 16;
+  const bool use_pc = P->precond == MFQ_PC_PTC;
+  const double tol2 = P->tol * P->tol;
+  GmBufs B;
+  auto cleanup = [&]() {
+    B.V.free_all();
+    B.Z.free_all();
+    B.w.free_all();
+    B.xsave.free_all();
+    release(B.st);
+    release(B.part);
+  };
+  const size_t fch = field_chunks<double>(g, n);
+  if (B.V.alloc(g, n * (m + 1)) || B.Z.alloc(g, n * m) || B.w.alloc(g, n) || B.xsave.alloc(g, n) ||
+      ensure(B.st, sizeof(GmState) * n) || ensure(B.part, sizeof(double) * 2 * (size_t)n * (m + 1) * ((2 * g.vh + 255) / 256))) {
+    cleanup();
+    return fail(MFQ_ERR_NOMEM, "FGMRES workspace");
+  }
+  std::vector<GmState> host(n);
+  const int nblk = (2 * g.vh + 255) / 256;
+  const dim3 grid(nblk, n), blk(256);
+  GmState* S = (GmState*)B.st.ptr;
+  double* part = (double*)B.part.ptr;
+  Field<double> V = B.V.view(g), Z = B.Z.view(g), W = B.w.view(g);
+  Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), r64 = w.r64.view(g), t64 = w.t64.view(g);
+  auto vj = [&](Field<double> base, int j) {
+    Field<double> f = base;
+    f.data += (size_t)j * fch;
+    return f;
+  };
+  const Shape sh = default_shape(n);
+  HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n);
+  a.coef = -h->lat.kappa;
+  // out = D^+ D in (FP64), t64 scratch
+  auto apply_a = [&](Field<double> in, Field<double> out) -> int {
+    a.in = a.self = in;
+    a.out = t64;
+    a.dagger = 0;
+    a.part = nullptr;
+    for (int par = 0; par < 2; ++par) {
+      a.par = par;
+      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+    }
+    a.in = a.self = t64;
+    a.out = out;
+    a.dagger = 1;
+    for (int par = 0; par < 2; ++par) {
+      a.par = par;
+      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+    }
+    return MFQ_OK;
+  };
+  auto norm_finish = [&](Field<double> f, int j, int which) -> int {
+    hipLaunchKernelGGL(gm_norm_kernel, grid, blk, 0, st, g, f, n, part);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(gm_norm_finish_kernel, dim3((n + 3) / 4), dim3(256), 0, st, part, nblk, n, S, j, which, tol2);
+    return hipGetLastError() == hipSuccess ? MFQ_OK : fail(MFQ_ERR_HIP, "gm_norm_finish");
+  };
+  int rc;
+  // x = 0, r = b, v_0 = b / |b|
+  HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, fch * sizeof(d2), st));
+  if ((rc = norm_finish(b64, 0, 1))) return cleanup(), rc;
+  hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, b64, vj(V, 0), n, S);
+  const int max_cycles = (P->max_iter + m - 1) / m;
+  double prev_worst = 1e300;
+  bool fell_back = false;
+  int status = MFQ_OK;
+  for (int cycle = 0;; ++cycle) {
+    for (int j = 0; j < m; ++j) {
+      if (use_pc) {
+        if ((rc = ptc_apply_fields(h, vj(V, j), vj(Z, j), n, st))) return cleanup(), rc;
+      } else {
+        HIPCHK(hipMemcpyAsync(vj(Z, j).data, vj(V, j).data, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+      }
+      if ((rc = apply_a(vj(Z, j), W))) return cleanup(), rc;
+      for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+        hipLaunchKernelGGL(gm_multidot_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, part);
+        hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 1) + 3) / 4), dim3(256), 0, st, part, nblk, j + 1,
+                           n, S, j, pass == 0 ? 1 : 0);
+        hipLaunchKernelGGL(gm_multiaxpy_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, S);
+      }
+      if ((rc = norm_finish(W, j, 0))) return cleanup(), rc;
+      hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, W, vj(V, j + 1), n, S);
+      hipLaunchKernelGGL(gm_givens_kernel, dim3((n + 63) / 64), dim3(64), 0, st, S, n, j, m, tol2);
+      HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(gm_solve_kernel, dim3((n + 63) / 64), dim3(64), 0, st, S, n);
+    hipLaunchKernelGGL(gm_xupdate_kernel, grid, blk, 0, st, g, Z, fch, x64, n, S);
+    // true residual r = b - A x, restart v_0 = r / |r|
+    a.in = a.self = x64;
+    a.out = t64;
+    a.dagger = 0;
+    for (int par = 0; par < 2; ++par) {
+      a.par = par;
+      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+    }
+    a.in = a.self = t64;
+    a.bvec = b64;
+    a.r64 = r64;
+    a.dagger = 1;
+    for (int par = 0; par < 2; ++par) {
+      a.par = par;
+      HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
+    }
+    if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
+    hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, r64, vj(V, 0), n, S);
+    HIPCHK(hipMemcpyAsync(host.data(), S, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool all_done = true, bad = false;
+    double worst = 0.0;
+    for (int r = 0; r < n; ++r) {
+      all_done = all_done && host[r].done;
+      if (!isfinite(host[r].rtrue2)) bad = true;
+      if (!host[r].done && host[r].bnorm2 > 0) {
+        const double rel = sqrt(host[r].rtrue2 / host[r].bnorm2);
+        if (rel > worst) worst = rel;
+      }
+    }
+    if (all_done) break;
+    // stagnation: a whole cycle that does not reduce the worst residual by 5%
+    if (bad || worst > 0.95 * prev_worst || cycle + 1 >= max_cycles) {
+      if (cycle + 1 >= max_cycles && !bad && worst <= 0.95 * prev_worst) {
+        status = MFQ_NOT_CONVERGED;
+        break;
+      }
+      fell_back = true;
+      break;
+    }
+    prev_worst = worst;
+  }
+  int cg_iters = 0;
+  if (fell_back) {
+    // CG on the remaining residual, A e = r with r = b - A x, then x += e.
+    // If the preconditioned solve produced NaN, CG starts again from x = 0.
+    bool bad = false;
+    for (int r = 0; r < n; ++r) bad = bad || !isfinite(host[r].rtrue2);
+    if (bad) {
+      HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, fch * sizeof(d2), st));
+      HIPCHK(hipMemcpyAsync(r64.data, b64.data, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    }
+    // tolerance for the residual system so that |b - A x| <= tol |b| for
+    // every RHS: tol * min_i |b_i| / |r_i|
+    double ratio = 1.0;
+    for (int r = 0; r < n; ++r)
+      if (!bad && host[r].rtrue2 > 0 && host[r].bnorm2 > 0)
+        ratio = fmin(ratio, sqrt(host[r].bnorm2 / host[r].rtrue2));
+    HIPCHK(hipMemcpyAsync(B.xsave.data.ptr, w.x64.data.ptr, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.w.data.ptr, w.b64.data.ptr, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, r64.data, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    mfq_solve_params Q = *P;
+    Q.precond = MFQ_PC_NONE;
+    Q.prec = MFQ_PREC_FP64;
+    Q.tol = fmax(fmin(P->tol * ratio, 0.5), 1e-15);
+    std::vector<mfq_solve_stats> cst(n);
+    rc = solve_packed(h, n, &Q, st, cst.data());
+    if (rc < 0) return cleanup(), rc;
+    for (int r = 0; r < n; ++r) cg_iters = cg_iters > cst[r].iters ? cg_iters : cst[r].iters;
+    hipLaunchKernelGGL(gm_add_kernel, grid, blk, 0, st, g, x64, B.xsave.view(g), n);
+    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, B.w.data.ptr, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    // final FP64 true residual against the original right-hand side
+    a.in = a.self = x64;
+    a.out = t64;
+    a.dagger = 0;
+    a.part = nullptr;
+    for (int par = 0; par < 2; ++par) {
+      a.par = par;
+      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+    }
+    a.in = a.self = t64;
+    a.bvec = b64;
+    a.r64 = r64;
+    a.dagger = 1;
+    for (int par = 0; par < 2; ++par) {
+      a.par = par;
+      HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
+    }
+    if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
+    HIPCHK(hipMemcpyAsync(host.data(), S, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
+    status = MFQ_FELL_BACK;
+    for (int r = 0; r < n; ++r)
+      if (!host[r].done) status = MFQ_NOT_CONVERGED;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int r = 0; r < n; ++r) {
+    if (stats) {
+      stats[r].iters = host[r].iters + cg_iters;
+      stats[r].reliable_updates = host[r].cycles;
+      stats[r].true_rel_resid = host[r].bnorm2 > 0 ? sqrt(host[r].rtrue2 / host[r].bnorm2) : 0.0;
+      stats[r].status = host[r].done ? (fell_back ? MFQ_FELL_BACK : MFQ_OK) : MFQ_NOT_CONVERGED;
+    }
+  }
+  cleanup();
+  return status;
+}
+
+}  // namespace mfq

@@ -1,0 +1,108 @@
+// The library handle and the host-side helpers shared by the translation
+// units that drive solves (single lattice and multi-lattice batch).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "mfq.h"
+
+namespace mfq {
+
+struct Workspace {
+  OwnedField<double> b64, x64, r64, t64, y64;
+  OwnedField<double> xd, rd, pd, td;
+  OwnedField<float> xs, rs, ps, ts;
+  OwnedField<_Float16> rh, ph, th;
+  DevBuf part, sc, sums, bad;
+  int cap_part = 0;  // RHS capacity of the partial-sum slots
+  int nblk_max = 0;
+  CgScalars* host_sc = nullptr;
+  int host_cap = 0;
+};
+
+// A captured run of k inner CG iterations.  The key holds everything the
+// captured kernel arguments depend on, so a stale graph never matches.
+struct GraphEntry {
+  std::vector<uintptr_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// Learned-preconditioner state (allocated on first use).
+struct PtcState {
+  DevBuf w_master;  // FP32 master weights: W1 then W2, interleaved complex
+  DevBuf w_infer;   // the same rounded to BF16 values (inference weights)
+  DevBuf adam_m, adam_v, grad, part, enorm2;
+  OwnedField<float> hid, y, gy, gh;
+  OwnedField<double> pr, pe;  // packed training pairs (residuals, errors)
+  int adam_t = 0;
+  bool have_weights = false;
+};
+
+struct TuneEntry {
+  int n, prec;
+  Shape sh;
+  float us;
+};
+
+}  // namespace mfq
+
+struct mfq_handle {
+  std::vector<mfq::TuneEntry> tuned;  // autotuned launch shapes, by (n_rhs, precision)
+  int autotune = 1;
+  mfq_lattice lat;
+  mfq::Geom g;
+  int n_slices;
+  mfq::DevBuf links64, links32, links16;
+  mfq::Workspace ws;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t cap_stream = nullptr;  // used only to capture graphs
+  std::vector<mfq::GraphEntry> graphs;
+  mfq::PtcState* ptc = nullptr;
+  int links_su3 = 0;  // every link is SU(3): the two-row FP32 / FP16 copies are valid
+};
+
+
+namespace mfq {
+
+int fail(int code, const std::string& msg);
+int fail_hip(hipError_t e, const char* what);
+uintptr_t bits(double v);
+void drop_graphs(mfq_handle* h);
+Links<double> links_d(mfq_handle* h);
+Links<float> links_f(mfq_handle* h);
+Links<_Float16> links_h(mfq_handle* h);
+int partials_ready(mfq_handle* h, int n_rhs);
+double* part_slot(mfq_handle* h, int slot);
+int ensure_fp64_fields(mfq_handle* h, int n);
+int check_params(const mfq_solve_params* P);
+int need_su3(mfq_handle* h, int prec, int precond);
+int pack_checked(mfq_handle* h, const double* canon, int n_rhs, int gamma5, hipStream_t st);
+int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
+// flexible GMRES with the learned (or identity) preconditioner (fgmres.hip)
+int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
+// learned preconditioner (ptc_host.hip)
+int ptc_apply_fields(mfq_handle* h, Field<double> in, Field<double> out, int n, hipStream_t st);
+
+template <typename S, typename SX>
+HopArgs<S, SX> hop_args(mfq_handle* h, Links<S> L, int n_rhs) {
+  HopArgs<S, SX> a;
+  memset((void*)&a, 0, sizeof(a));
+  a.g = h->g;
+  a.links = L;
+  a.n_rhs = n_rhs;
+  a.skip_state = 3;
+  return a;
+}
+
+}  // namespace mfq
+
+#define HIPCHK(...)                                          \
+  do {                                                       \
+    hipError_t e_ = (__VA_ARGS__);                           \
+    if (e_ != hipSuccess) return fail_hip(e_, #__VA_ARGS__); \
+  } while (0)

@@ -1,0 +1,252 @@
+// Device implementation of the Wilson hopping term and its fused epilogues,
+// shared by the single-lattice kernels and the multi-lattice persistent
+// kernels.
+//
+// H psi(n) = sum_mu [ (1 - g_mu) U_mu(n) psi(n+mu) + (1 + g_mu) U_mu(n-mu)^+ psi(n-mu) ]
+// and its adjoint (projector signs swapped); D = 1 - kappa H.
+#pragma once
+
+#include "internal.h"
+
+namespace mfq {
+
+template <typename S>
+struct Compute {
+  using T = float;
+};
+template <>
+struct Compute<double> {
+  using T = double;
+};
+
+template <typename T>
+__device__ __forceinline__ void zero(Spinor<T>& a) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) a.v[c] = {(T)0, (T)0};
+}
+
+template <typename T>
+__device__ __forceinline__ double snorm2(const Spinor<T>& a) {
+  T s = 0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) s += norm2(a.v[c]);
+  return (double)s;
+}
+
+// Partial sum of v over the sites of this workgroup, one value per RHS row
+// (row = threadIdx.y, RHS r = r0 + row), stored at part[r * nblk + tile].
+// A wavefront holds one RHS (blockDim.x is a multiple of 64).
+__device__ __forceinline__ void block_partial(double v, double* part, int n_rhs, int r0, int tile, int nblk) {
+  __shared__ double ws[16];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  v = wave_sum(v);
+  if ((tid & 63) == 0) ws[tid >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int wpr = blockDim.x >> 6;
+    double s = 0.0;
+    for (int k = 0; k < wpr; ++k) s += ws[threadIdx.y * wpr + k];
+    const int r = r0 + threadIdx.y;
+    if (r < n_rhs) part[(long)r * nblk + tile] = s;
+  }
+  __syncthreads();
+}
+
+// One direction mu of the hopping term: forward hop from n+mu through U_mu(n),
+// backward hop from n-mu through U_mu(n-mu)^+.  sgf / sgb are the projector
+// signs (-1 / +1 for H, +1 / -1 for H^+).
+template <int MU, typename S, typename SX, typename T>
+__device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Coords& c, int s, int r,
+                                        T sgf, T sgb, Spinor<T>& acc) {
+  const Geom& g = a.g;
+  const int po = 1 - a.par;
+  {  // forward
+    int x = c.x, y = c.y, z = c.z, t = c.t;
+    T sgn = (T)1;
+    bool ok = true;
+    if constexpr (MU == 0) {
+      t = c.t + 1;
+      if (t == g.td) {
+        if (g.bc == BC_SF) ok = false;
+        t = 0;
+        if (g.bc == BC_ANTIPERIODIC) sgn = (T)-1;
+      }
+    } else if constexpr (MU == 1) {
+      x = (c.x + 1 == g.lx) ? 0 : c.x + 1;
+    } else if constexpr (MU == 2) {
+      y = (c.y + 1 == g.ly) ? 0 : c.y + 1;
+    } else {
+      z = (c.z + 1 == g.lz) ? 0 : c.z + 1;
+    }
+    if (ok) {
+      Spinor<T> nb;
+      load_spinor(a.in, r, po, half_index(g, x, y, z, t), nb);
+      cpx<T> u[9];
+      load_link(a.links, a.par, MU, s, u);
+      cpx<T> h0[3], h1[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) project<MU>(nb, sgf, k, h0[k], h1[k]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        cpx<T> g0 = cmul(u[3 * i], h0[0]) + cmul(u[3 * i + 1], h0[1]) + cmul(u[3 * i + 2], h0[2]);
+        cpx<T> g1 = cmul(u[3 * i], h1[0]) + cmul(u[3 * i + 1], h1[1]) + cmul(u[3 * i + 2], h1[2]);
+        reconstruct<MU>(acc, sgf, i, sgn * g0, sgn * g1);
+      }
+    }
+  }
+  {  // backward
+    int x = c.x, y = c.y, z = c.z, t = c.t;
+    T sgn = (T)1;
+    bool ok = true;
+    if constexpr (MU == 0) {
+      t = c.t - 1;
+      if (t < 0) {
+        if (g.bc == BC_SF) ok = false;
+        t = g.td - 1;
+        if (g.bc == BC_ANTIPERIODIC) sgn = (T)-1;
+      }
+    } else if constexpr (MU == 1) {
+      x = (c.x == 0) ? g.lx - 1 : c.x - 1;
+    } else if constexpr (MU == 2) {
+      y = (c.y == 0) ? g.ly - 1 : c.y - 1;
+    } else {
+      z = (c.z == 0) ? g.lz - 1 : c.z - 1;
+    }
+    if (ok) {
+      const int sb = half_index(g, x, y, z, t);
+      Spinor<T> nb;
+      load_spinor(a.in, r, po, sb, nb);
+      cpx<T> u[9];
+      load_link(a.links, po, MU, sb, u);
+      cpx<T> h0[3], h1[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) project<MU>(nb, sgb, k, h0[k], h1[k]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {  // (U^+)_{ik} = conj(U_{ki})
+        cpx<T> g0 = cjmul(u[i], h0[0]) + cjmul(u[3 + i], h0[1]) + cjmul(u[6 + i], h0[2]);
+        cpx<T> g1 = cjmul(u[i], h1[0]) + cjmul(u[3 + i], h1[1]) + cjmul(u[6 + i], h1[2]);
+        reconstruct<MU>(acc, sgb, i, sgn * g0, sgn * g1);
+      }
+    }
+  }
+}
+
+// The per-RHS CG scalar recursion, applied once the reduction `sum` of the
+// partials of one kernel pair is known (see the FIN_* codes).
+__device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double sum, double tol2, double delta2) {
+  const bool finite = isfinite(sum);
+  switch (fin) {
+    case FIN_ALPHA:
+      s.rp = 0;
+      s.pap = sum;
+      if (s.state == ST_ACTIVE && finite && sum > 0.0) {
+        s.alpha = s.rho / sum;
+      } else {
+        if (s.state == ST_ACTIVE) s.state = ST_CHECK;  // breakdown: re-check truth
+        s.alpha = 0.0;
+      }
+      break;
+    case FIN_BETA:
+      if (s.state == ST_ACTIVE) {
+        s.beta = sum / s.rho;
+        s.rho = sum;
+        s.iters += 1;
+        if (!finite || sum <= tol2 * s.bnorm2) s.state = ST_CHECK;
+        if (sum < delta2 * s.rho_ru) s.upd = 1;
+      } else {
+        s.beta = 0.0;
+      }
+      break;
+    case FIN_TRUE:
+      if (s.state != ST_DONE) {
+        // an RHS whose recursion claimed convergence (or broke down) keeps a
+        // search direction orthogonal to its residual: restart it with p = r
+        const int was_check = s.state == ST_CHECK;
+        s.rtrue2 = sum;
+        s.n_true += 1;
+        if (sum <= tol2 * s.bnorm2) {
+          s.state = ST_DONE;
+        } else {
+          s.state = ST_ACTIVE;
+          s.rho = sum;
+          s.rho_ru = sum;
+          s.rp = was_check;
+        }
+        s.upd = 0;
+      }
+      break;
+    case FIN_INIT:
+      s.bnorm2 = sum;
+      s.rho = s.rho_ru = s.rtrue2 = sum;
+      s.alpha = s.beta = s.pap = 0.0;
+      s.iters = s.upd = s.n_true = s.rp = 0;
+      s.state = sum > 0.0 ? ST_ACTIVE : ST_DONE;
+      break;
+  }
+}
+
+
+// The hopping term at output site s (parity a.par) for RHS r, followed by the
+// epilogue; returns the value this site contributes to the partial sum.
+template <int EPI, typename S, typename SX>
+__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int s, int r) {
+  using T = typename Compute<S>::T;
+  double red = 0.0;
+  Spinor<T> acc;
+  zero(acc);
+  const Coords c = site_coords(a.g, s, a.par);
+  const T sgf = a.dagger ? (T)1 : (T)-1;
+  const T sgb = -sgf;
+  hop_dir<0>(a, c, s, r, sgf, sgb, acc);
+  hop_dir<1>(a, c, s, r, sgf, sgb, acc);
+  hop_dir<2>(a, c, s, r, sgf, sgb, acc);
+  hop_dir<3>(a, c, s, r, sgf, sgb, acc);
+  const T b = (T)a.coef;
+  if constexpr (EPI == EPI_HOP) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc.v[k] = b * acc.v[k];
+    store_spinor(a.out, r, a.par, s, acc);
+  } else if constexpr (EPI == EPI_D) {
+    Spinor<T> self;
+    load_spinor(a.self, r, a.par, s, self);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc.v[k] = self.v[k] + b * acc.v[k];
+    store_spinor(a.out, r, a.par, s, acc);
+    red = snorm2(acc);
+  } else if constexpr (EPI == EPI_CGUPD) {
+    using TX = typename Compute<SX>::T;
+    Spinor<T> self, rr, pp;
+    Spinor<TX> xx;
+    load_spinor(a.self, r, a.par, s, self);
+    load_spinor(a.out, r, a.par, s, rr);
+    load_spinor(a.p, r, a.par, s, pp);
+    load_spinor(a.x, r, a.par, s, xx);
+    const double al = a.sc[r].alpha;
+    const T alpha = (T)al;
+    const TX alx = (TX)al;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const cpx<T> ap = self.v[k] + b * acc.v[k];
+      rr.v[k] = rr.v[k] - alpha * ap;
+      xx.v[k] = xx.v[k] + alx * cpx<TX>{(TX)pp.v[k].re, (TX)pp.v[k].im};
+    }
+    store_spinor(a.out, r, a.par, s, rr);
+    store_spinor(a.x, r, a.par, s, xx);
+    red = snorm2(rr);
+  } else {  // EPI_RES (FP64)
+    Spinor<double> self, bb;
+    load_spinor(a.self, r, a.par, s, self);
+    load_spinor(a.bvec, r, a.par, s, bb);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const cpx<double> ap = {(double)self.v[k].re + (double)b * (double)acc.v[k].re,
+                              (double)self.v[k].im + (double)b * (double)acc.v[k].im};
+      bb.v[k] = bb.v[k] - ap;
+    }
+    store_spinor(a.r64, r, a.par, s, bb);
+    red = snorm2(bb);
+  }
+  return red;
+}
+
+}  // namespace mfq

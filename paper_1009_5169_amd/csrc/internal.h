@@ -28,6 +28,8 @@ struct CgScalars {
   int iters;
   int upd;    // reliable update requested (residual dropped by delta)
   int n_true; // true-residual evaluations
+  int rp;     // restart the search direction at the next restart (p = r)
+  int pad2;
 };
 
 enum : int {
@@ -53,8 +55,9 @@ struct Partials {
 
 // Launch shape of the site x RHS kernels.
 struct Shape {
-  int sb;  // sites per workgroup (multiple of 64)
-  int nr;  // right-hand sides per workgroup
+  int sb;   // sites per workgroup (multiple of 64)
+  int nr;   // right-hand sides per workgroup
+  int xcd;  // remap workgroups so each XCD walks a contiguous chunk of sites
 };
 
 Shape default_shape(int n_rhs);
@@ -75,6 +78,7 @@ struct HopArgs {
   const CgScalars* sc; // per-RHS scalars (alpha, state) or null
   double* part;        // partial sums [n_rhs][gridDim.x] or null
   int par, n_rhs, dagger, skip_state;
+  int xcd;             // set by the launcher from the Shape
   double coef;         // coefficient of the hopping term
 };
 
@@ -110,7 +114,7 @@ hipError_t launch_unpack_spinor(const Geom& g, Field<double> f, double* canon, i
                                 hipStream_t st);
 template <typename S>
 hipError_t launch_pack_links(const Geom& g, const double* canon, typename Store<S>::link_elem* out,
-                             int* bad_flag, hipStream_t st);
+                             int* bad_flag, int comp, int su3_check, hipStream_t st);
 
 // Fermion force: G_mu(n) summed over RHS, canonical FP64 output.
 hipError_t launch_force(const Geom& g, Links<double> links, Field<double> X, Field<double> Y,

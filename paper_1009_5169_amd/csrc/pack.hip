@@ -4,6 +4,8 @@
 // Canonical spinor: [rhs][t][z][y][x][spin 4][colour 3] complex128 over the
 // dynamical slices; canonical links and force: [mu][x0][z][y][x][3][3]
 // complex128 over the stored link slices (x0 = 0..T for SF, 0..T-1 else).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mfq {
@@ -71,8 +73,12 @@ __global__ void unpack_spinor_kernel(Geom g, Field<double> f, d2* canon, int n_r
 }
 
 // Links on the dynamical sites only: U_mu(n) for every dynamical n, mu.
+// bad |= 1 for non-finite links; with su3_check, bad |= 2 for links that are
+// not SU(3) to 1e-10 (|U U^+ - 1| or |det U - 1|), which rules out the
+// two-row layout the FP32 / FP16 copies use (comp = 1 writes that layout).
 template <typename S>
-__global__ void pack_links_kernel(Geom g, const d2* canon, typename Store<S>::link_elem* out, int* bad) {
+__global__ void pack_links_kernel(Geom g, const d2* canon, typename Store<S>::link_elem* out, int* bad, int comp,
+                                  int su3_check) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int mu = blockIdx.y;
   const int vd = 2 * g.vh;
@@ -84,17 +90,55 @@ __global__ void pack_links_kernel(Geom g, const d2* canon, typename Store<S>::li
   const long n_slice_sites = (long)g.lx * g.ly * g.lz;
   const int n_slices = g.td + (g.bc == BC_SF ? 2 : 0);
   const d2* src = canon + (((long)mu * n_slices + (t + g.t0)) * n_slice_sites + q % n_slice_sites) * 9;
+  cpx<double> u[9];
   bool finite = true;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     d2 v = src[k];
     finite = finite && isfinite(v.x) && isfinite(v.y);
-    typename Store<S>::link_elem e;
-    e.x = (S)v.x;
-    e.y = (S)v.y;
-    out[((long)(par * 4 + mu) * 9 + k) * g.vh + s] = e;
+    u[k] = {v.x, v.y};
   }
   if (!finite && bad) atomicOr(bad, 1);
+  if (su3_check && bad) {
+    double dev = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        cpx<double> acc = {a == b ? -1.0 : 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc = acc + cjmul(u[3 * b + k], u[3 * a + k]);  // (U U^+)_ab - delta
+        dev = fmax(dev, fabs(acc.re) + fabs(acc.im));
+      }
+    const cpx<double> det = cmul(u[0], cmul(u[4], u[8]) - cmul(u[5], u[7])) -
+                            cmul(u[1], cmul(u[3], u[8]) - cmul(u[5], u[6])) +
+                            cmul(u[2], cmul(u[3], u[7]) - cmul(u[4], u[6]));
+    dev = fmax(dev, fabs(det.re - 1.0) + fabs(det.im));
+    if (!(dev <= 1e-10)) atomicOr(bad, 2);
+  }
+  if constexpr (sizeof(S) != 8) {
+    if (comp) {
+      using C = typename std::conditional<sizeof(S) == 4, f4, h4>::type;
+      C* co = (C*)out;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C e;
+        e.x = (S)u[2 * c].re;
+        e.y = (S)u[2 * c].im;
+        e.z = (S)u[2 * c + 1].re;
+        e.w = (S)u[2 * c + 1].im;
+        co[((long)(par * 4 + mu) * 3 + c) * g.vh + s] = e;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    typename Store<S>::link_elem e;
+    e.x = (S)u[k].re;
+    e.y = (S)u[k].im;
+    out[((long)(par * 4 + mu) * 9 + k) * g.vh + s] = e;
+  }
 }
 
 template <typename S>
@@ -111,18 +155,18 @@ hipError_t launch_unpack_spinor(const Geom& g, Field<double> f, double* canon, i
 }
 template <typename S>
 hipError_t launch_pack_links(const Geom& g, const double* canon, typename Store<S>::link_elem* out, int* bad,
-                             hipStream_t st) {
+                             int comp, int su3_check, hipStream_t st) {
   dim3 grid((2 * g.vh + 255) / 256, 4);
-  hipLaunchKernelGGL((pack_links_kernel<S>), grid, dim3(256), 0, st, g, (const d2*)canon, out, bad);
+  hipLaunchKernelGGL((pack_links_kernel<S>), grid, dim3(256), 0, st, g, (const d2*)canon, out, bad, comp, su3_check);
   return hipGetLastError();
 }
 
 template hipError_t launch_pack_spinor<double>(const Geom&, const double*, Field<double>, int, int, int*, hipStream_t);
 template hipError_t launch_pack_spinor<float>(const Geom&, const double*, Field<float>, int, int, int*, hipStream_t);
 template hipError_t launch_pack_spinor<_Float16>(const Geom&, const double*, Field<_Float16>, int, int, int*, hipStream_t);
-template hipError_t launch_pack_links<double>(const Geom&, const double*, d2*, int*, hipStream_t);
-template hipError_t launch_pack_links<float>(const Geom&, const double*, f2*, int*, hipStream_t);
-template hipError_t launch_pack_links<_Float16>(const Geom&, const double*, h2*, int*, hipStream_t);
+template hipError_t launch_pack_links<double>(const Geom&, const double*, d2*, int*, int, int, hipStream_t);
+template hipError_t launch_pack_links<float>(const Geom&, const double*, f2*, int*, int, int, hipStream_t);
+template hipError_t launch_pack_links<_Float16>(const Geom&, const double*, h2*, int*, int, int, hipStream_t);
 
 // ------------------------------------------------------------------ force
 // For the link (n, mu), with X = D^-1 phi and Y = (D^+)^-1 X per RHS i:

@@ -1,0 +1,402 @@
+// Gauge-covariant parallel-transport convolution (PTC) network: the learned
+// preconditioner of the flexible GMRES solve.
+//
+// Paths p = 0..8: p = 0 the identity, p = 1 + mu the forward transport
+// (T_p psi)(n) = U_mu(n) psi(n + mu), p = 5 + mu the backward transport
+// (T_p psi)(n) = U_mu(n - mu)^+ psi(n - mu), with the Wilson operator's time
+// boundary rules.  A layer maps channels c -> c':
+//     psi'[c'](n) = sum_c sum_p W[p][c'][c] (T_p psi[c])(n),
+// W a complex 4x4 spin matrix.  The network is 1 -> 8 -> 1 channels, linear.
+// Layer 1 transports then mixes; layer 2 mixes then transports (W acts on
+// spin, T on colour, so they commute), which needs 8 transports per site
+// instead of 64.  The forward, backward (adjoint and weight gradient) and
+// Adam kernels here are what the library trains the network with.
+//
+// Channel fields are FP32 Field<float> with virtual RHS index r * C + c.
+#include "internal.h"
+#include "hop_impl.h"
+#include "ptc.h"
+
+namespace mfq {
+
+// Transport along path p (1..8) from the neighbour of (c) to site n: returns
+// false across an SF boundary.  nb_site/nb_par give the neighbour; the caller
+// loads the neighbour spinor and applies U or U^+.
+struct PathHop {
+  int site;      // neighbour half-lattice index (parity 1 - par)
+  int link_par;  // parity of the site that holds the link
+  int link_site;
+  float sgn;
+  bool ok;
+};
+
+__device__ __forceinline__ PathHop path_hop(const Geom& g, const Coords& c, int s, int par, int mu, bool fwd) {
+  PathHop h;
+  int x = c.x, y = c.y, z = c.z, t = c.t;
+  h.sgn = 1.f;
+  h.ok = true;
+  const int d = fwd ? 1 : -1;
+  if (mu == 0) {
+    t += d;
+    if (t == g.td || t < 0) {
+      if (g.bc == BC_SF) h.ok = false;
+      t = t < 0 ? g.td - 1 : 0;
+      if (g.bc == BC_ANTIPERIODIC) h.sgn = -1.f;
+    }
+  } else if (mu == 1) {
+    x = (x + d + g.lx) % g.lx;
+  } else if (mu == 2) {
+    y = (y + d + g.ly) % g.ly;
+  } else {
+    z = (z + d + g.lz) % g.lz;
+  }
+  h.site = half_index(g, x, y, z, t);
+  h.link_par = fwd ? par : 1 - par;
+  h.link_site = fwd ? s : h.site;
+  return h;
+}
+
+// out = U psi (fwd) or U^+ psi (bwd), scaled by sgn
+template <typename T>
+__device__ __forceinline__ void colour_mul(const cpx<T> u[9], bool dag, T sgn, const Spinor<T>& in, Spinor<T>& out) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<T> acc = {(T)0, (T)0};
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        acc = acc + (dag ? cjmul(u[3 * b + a], in.v[3 * sp + b]) : cmul(u[3 * a + b], in.v[3 * sp + b]));
+      out.v[3 * sp + a] = sgn * acc;
+    }
+}
+
+// acc += W psi on spin (W: 16 complex, row-major [s'][s])
+__device__ __forceinline__ void spin_mul_add(const f2* W, const Spinor<float>& in, Spinor<float>& acc) {
+#pragma unroll
+  for (int so = 0; so < 4; ++so)
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      const f2 w = W[4 * so + si];
+      const cpx<float> wc = {w.x, w.y};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc.v[3 * so + a] = acc.v[3 * so + a] + cmul(wc, in.v[3 * si + a]);
+    }
+}
+
+// acc += W^+ psi on spin
+__device__ __forceinline__ void spin_mul_add_dag(const f2* W, const Spinor<float>& in, Spinor<float>& acc) {
+#pragma unroll
+  for (int so = 0; so < 4; ++so)
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      const f2 w = W[4 * si + so];  // (W^+)_{so,si} = conj(W_{si,so})
+      const cpx<float> wc = {w.x, w.y};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc.v[3 * so + a] = acc.v[3 * so + a] + cjmul(wc, in.v[3 * si + a]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero_sp(Spinor<T>& a) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a.v[k] = {(T)0, (T)0};
+}
+
+// T_p psi at site (s, par) for field f, virtual RHS index vr
+template <typename SI>
+__device__ __forceinline__ void transported(const Geom& g, const Links<float>& L, const Field<SI>& f, int vr, int p,
+                                            int s, int par, const Coords& c, Spinor<float>& out) {
+  if (p == 0) {
+    load_spinor(f, vr, par, s, out);
+    return;
+  }
+  const int mu = p <= 4 ? p - 1 : p - 5;
+  const bool fwd = p <= 4;
+  const PathHop h = path_hop(g, c, s, par, mu, fwd);
+  if (!h.ok) {
+    zero_sp(out);
+    return;
+  }
+  Spinor<float> nb;
+  load_spinor(f, vr, 1 - par, h.site, nb);
+  cpx<float> u[9];
+  load_link(L, h.link_par, mu, h.link_site, u);
+  colour_mul(u, !fwd, h.sgn, nb, out);
+}
+
+#define PTC_LANE                                                   \
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;             \
+  const int r = blockIdx.y;                                        \
+  if (q >= 2 * g.vh || r >= n_rhs) return;                         \
+  const int par = q >= g.vh ? 1 : 0;                               \
+  const int s = q - par * g.vh;                                    \
+  const Coords c = site_coords(g, s, par);
+
+// Layer 1 (1 -> 8): hid[r*8 + c'] = sum_p W1[p][c'] (T_p in_r); grid.z picks
+// a group of 4 output channels.
+template <typename SI>
+__global__ __launch_bounds__(256) void ptc_l1_kernel(Geom g, Links<float> L, Field<SI> in, Field<float> hid,
+                                                     const f2* W1, int n_rhs, float scale) {
+  PTC_LANE
+  const int c0 = blockIdx.z * 4;
+  Spinor<float> acc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) zero_sp(acc[k]);
+  for (int p = 0; p < PTC_PATHS; ++p) {
+    Spinor<float> t;
+    transported(g, L, in, r, p, s, par, c, t);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) spin_mul_add(W1 + (p * PTC_HIDDEN + c0 + k) * 16, t, acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int j = 0; j < 12; ++j) acc[k].v[j] = scale * acc[k].v[j];
+    store_spinor(hid, r * PTC_HIDDEN + c0 + k, par, s, acc[k]);
+  }
+}
+
+// Layer 2 (8 -> 1): out_r = sum_p T_p chi_p, chi_p = sum_c W2[p][c] hid[r*8+c].
+template <typename SO>
+__global__ __launch_bounds__(256) void ptc_l2_kernel(Geom g, Links<float> L, Field<float> hid, Field<SO> out,
+                                                     const f2* W2, int n_rhs, float scale) {
+  PTC_LANE
+  Spinor<float> acc;
+  zero_sp(acc);
+  for (int p = 0; p < PTC_PATHS; ++p) {
+    int ms = s, mpar = par;
+    PathHop h;
+    int mu = 0;
+    bool fwd = true;
+    if (p > 0) {
+      mu = p <= 4 ? p - 1 : p - 5;
+      fwd = p <= 4;
+      h = path_hop(g, c, s, par, mu, fwd);
+      if (!h.ok) continue;
+      ms = h.site;
+      mpar = 1 - par;
+    }
+    Spinor<float> chi;
+    zero_sp(chi);
+    for (int k = 0; k < PTC_HIDDEN; ++k) {
+      Spinor<float> x;
+      load_spinor(hid, r * PTC_HIDDEN + k, mpar, ms, x);
+      spin_mul_add(W2 + (p * PTC_HIDDEN + k) * 16, x, chi);
+    }
+    if (p == 0) {
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc.v[j] = acc.v[j] + chi.v[j];
+    } else {
+      cpx<float> u[9];
+      load_link(L, h.link_par, mu, h.link_site, u);
+      Spinor<float> t;
+      colour_mul(u, !fwd, h.sgn, chi, t);
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc.v[j] = acc.v[j] + t.v[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 12; ++j) acc.v[j] = scale * acc.v[j];
+  store_spinor(out, r, par, s, acc);
+}
+
+template <typename SI, typename SO>
+hipError_t ptc_forward(const Geom& g, Links<float> L, Field<SI> in, Field<float> hid, Field<SO> out, const f2* W1,
+                       const f2* W2, int n_rhs, float in_scale, float out_scale, hipStream_t st) {
+  const dim3 grid1((2 * g.vh + 255) / 256, n_rhs, PTC_HIDDEN / 4);
+  hipLaunchKernelGGL((ptc_l1_kernel<SI>), grid1, dim3(256), 0, st, g, L, in, hid, W1, n_rhs, in_scale);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid2((2 * g.vh + 255) / 256, n_rhs);
+  hipLaunchKernelGGL((ptc_l2_kernel<SO>), grid2, dim3(256), 0, st, g, L, hid, out, W2, n_rhs, out_scale);
+  return hipGetLastError();
+}
+
+template hipError_t ptc_forward<double, double>(const Geom&, Links<float>, Field<double>, Field<float>, Field<double>,
+                                                const f2*, const f2*, int, float, float, hipStream_t);
+template hipError_t ptc_forward<double, float>(const Geom&, Links<float>, Field<double>, Field<float>, Field<float>,
+                                               const f2*, const f2*, int, float, float, hipStream_t);
+template hipError_t ptc_forward<float, float>(const Geom&, Links<float>, Field<float>, Field<float>, Field<float>,
+                                              const f2*, const f2*, int, float, float, hipStream_t);
+
+}  // namespace mfq
+
+namespace mfq {
+
+// ---------------------------------------------------------------- backward
+// Adjoint of layer 2 in its input.  T_p^+ = T_pbar (the forward transport's
+// adjoint is the backward one), and W commutes with transports, so
+//   gh[c](n) = sum_p W2[p][c]^+ (T_pbar gy)(n).
+__global__ __launch_bounds__(256) void ptc_adj2_kernel(Geom g, Links<float> L, Field<float> gy, Field<float> gh,
+                                                       const f2* W2, int n_rhs) {
+  PTC_LANE
+  const int c0 = blockIdx.z * 4;
+  Spinor<float> acc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) zero_sp(acc[k]);
+  for (int p = 0; p < PTC_PATHS; ++p) {
+    const int pbar = p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4);
+    Spinor<float> t;
+    transported(g, L, gy, r, pbar, s, par, c, t);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) spin_mul_add_dag(W2 + (p * PTC_HIDDEN + c0 + k) * 16, t, acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) store_spinor(gh, r * PTC_HIDDEN + c0 + k, par, s, acc[k]);
+}
+
+hipError_t ptc_adjoint2(const Geom& g, Links<float> L, Field<float> gy, Field<float> gh, const f2* W2, int n_pairs,
+                        hipStream_t st) {
+  const dim3 grid((2 * g.vh + 255) / 256, n_pairs, PTC_HIDDEN / 4);
+  hipLaunchKernelGGL(ptc_adj2_kernel, grid, dim3(256), 0, st, g, L, gy, gh, W2, n_pairs);
+  return hipGetLastError();
+}
+
+// One (path, c_out, c_in) weight-gradient block per blockIdx.y; each thread
+// sums its site's spin outer product over colours and pairs; the workgroup
+// reduces in FP64 and writes one partial per workgroup.
+template <typename SX>
+__global__ __launch_bounds__(256) void ptc_wgrad_kernel(Geom g, Links<float> L, Field<SX> x, int c_in, Field<float> gf,
+                                                        int c_out, int n_pairs, double* part) {
+  __shared__ double ws[4][32];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = blockIdx.y;  // (p * c_out + co) * c_in + ci
+  const int ci = idx % c_in;
+  const int co = (idx / c_in) % c_out;
+  const int p = idx / (c_in * c_out);
+  float acc[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+  if (q < 2 * g.vh) {
+    const int par = q >= g.vh ? 1 : 0;
+    const int s = q - par * g.vh;
+    const Coords c = site_coords(g, s, par);
+    for (int k = 0; k < n_pairs; ++k) {
+      Spinor<float> t, gg;
+      transported(g, L, x, k * c_in + ci, p, s, par, c, t);
+      load_spinor(gf, k * c_out + co, par, s, gg);
+#pragma unroll
+      for (int so = 0; so < 4; ++so)
+#pragma unroll
+        for (int si = 0; si < 4; ++si) {
+          cpx<float> o = {0.f, 0.f};
+#pragma unroll
+          for (int a = 0; a < 3; ++a) o = o + cjmul(t.v[3 * si + a], gg.v[3 * so + a]);
+          acc[2 * (4 * so + si)] += o.re;
+          acc[2 * (4 * so + si) + 1] += o.im;
+        }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const double v = wave_sum((double)acc[k]);
+    if (lane == 0) ws[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const double v = ((ws[0][threadIdx.x] + ws[1][threadIdx.x]) + ws[2][threadIdx.x]) + ws[3][threadIdx.x];
+    part[((long)idx * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = v;
+  }
+}
+
+__global__ void ptc_grad_reduce_kernel(const double* part, int nblk, int n_idx, double* grad) {
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // one wave per (idx, component)
+  const int lane = threadIdx.x & 63;
+  if (w >= n_idx * 32) return;
+  const int idx = w / 32, k = w % 32;
+  double v = 0.0;
+  for (int j = lane; j < nblk; j += 64) v += part[((long)idx * nblk + j) * 32 + k];
+  v = wave_sum(v);
+  if (lane == 0) grad[(long)idx * 32 + k] = v;
+}
+
+template <typename SX>
+hipError_t ptc_weight_grad(const Geom& g, Links<float> L, Field<SX> x, int c_in, Field<float> gf, int c_out,
+                           int n_pairs, double* part, double* grad, hipStream_t st) {
+  const int nblk = (2 * g.vh + 255) / 256;
+  const int n_idx = PTC_PATHS * c_in * c_out;
+  hipLaunchKernelGGL((ptc_wgrad_kernel<SX>), dim3(nblk, n_idx), dim3(256), 0, st, g, L, x, c_in, gf, c_out, n_pairs,
+                     part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int waves = n_idx * 32;
+  hipLaunchKernelGGL(ptc_grad_reduce_kernel, dim3((waves + 3) / 4), dim3(256), 0, st, part, nblk, n_idx, grad);
+  return hipGetLastError();
+}
+
+template hipError_t ptc_weight_grad<double>(const Geom&, Links<float>, Field<double>, int, Field<float>, int, int,
+                                            double*, double*, hipStream_t);
+template hipError_t ptc_weight_grad<float>(const Geom&, Links<float>, Field<float>, int, Field<float>, int, int,
+                                           double*, double*, hipStream_t);
+
+__global__ __launch_bounds__(256) void ptc_loss_kernel(Geom g, Field<float> y, Field<double> e, const double* enorm2,
+                                                       Field<float> gy, int n_rhs, double* part) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  double red = 0.0;
+  if (q < 2 * g.vh) {
+    const int par = q >= g.vh ? 1 : 0;
+    const int s = q - par * g.vh;
+    Spinor<float> yy;
+    Spinor<double> ee;
+    load_spinor(y, r, par, s, yy);
+    load_spinor(e, r, par, s, ee);
+    const double en = enorm2[r] > 0.0 ? enorm2[r] : 1.0;  // a zero error contributes |y|^2
+    const float sc = (float)(2.0 / (n_rhs * en));
+    Spinor<float> d;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double dr = (double)yy.v[k].re - ee.v[k].re, di = (double)yy.v[k].im - ee.v[k].im;
+      red += dr * dr + di * di;
+      d.v[k] = {sc * (float)dr, sc * (float)di};
+    }
+    red /= en;
+    store_spinor(gy, r, par, s, d);
+  }
+  red = wave_sum(red);
+  __shared__ double ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = red;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long)r * gridDim.x + blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+hipError_t ptc_loss_grad_out(const Geom& g, Field<float> y, Field<double> e, const double* enorm2, Field<float> gy,
+                             int n_pairs, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(ptc_loss_kernel, dim3((2 * g.vh + 255) / 256, n_pairs), dim3(256), 0, st, g, y, e, enorm2, gy,
+                     n_pairs, part);
+  return hipGetLastError();
+}
+
+// Round to the nearest BF16 value (ties to even), kept in an FP32 register.
+__device__ __forceinline__ float round_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+__global__ void ptc_adam_kernel(float* w, const double* grad, float* m, float* v, int n_real, int t, float lr, float b1,
+                                float b2, float eps, float* w_infer) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_real) return;
+  const float gr = (float)grad[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gr;
+  const float vi = b2 * v[i] + (1.f - b2) * gr * gr;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / (1.f - powf(b1, (float)t));
+  const float vh = vi / (1.f - powf(b2, (float)t));
+  const float wi = w[i] - lr * mh / (sqrtf(vh) + eps);
+  w[i] = wi;
+  w_infer[i] = round_bf16(wi);
+}
+
+hipError_t ptc_adam(float* w, const double* grad, float* m, float* v, int n_real, int t, float lr, float b1, float b2,
+                    float eps, f2* w_infer, hipStream_t st) {
+  hipLaunchKernelGGL(ptc_adam_kernel, dim3((n_real + 255) / 256), dim3(256), 0, st, w, grad, m, v, n_real, t, lr, b1,
+                     b2, eps, (float*)w_infer);
+  return hipGetLastError();
+}
+
+}  // namespace mfq

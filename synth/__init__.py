@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Sequence
 
 import numpy as np
@@ -78,12 +79,31 @@ def spinor_shape(dims, bc, n_rhs):
     return (int(n_rhs), spinor_slices(dims, bc), lz, ly, lx, 4, 3)
 
 
-def _random_su3(rng: np.random.Generator, n: int, eps: float) -> np.ndarray:
-    """n matrices exp(i eps H), H = sum_a h_a lambda_a/2, h_a ~ N(0,1)."""
-    h = rng.standard_normal((n, 8))
+def _expi_herm(h: np.ndarray, eps: float) -> np.ndarray:
+    """exp(i eps H) for the su(3) coefficient rows h (H = sum_a h_a lambda_a/2)."""
     herm = np.einsum("na,aij->nij", h, _GELL_MANN / 2)
     w, v = np.linalg.eigh(herm)
     return np.einsum("nij,nj,nkj->nik", v, np.exp(1j * eps * w), v.conj())
+
+
+_PARALLEL_MIN = 200_000
+
+
+def _random_su3(rng: np.random.Generator, n: int, eps: float) -> np.ndarray:
+    """n matrices exp(i eps H), H = sum_a h_a lambda_a/2, h_a ~ N(0,1).
+
+    The Gaussian draw happens first; for large n the eigendecompositions run
+    in threads over chunks (LAPACK releases the GIL).  The result does not
+    depend on the number of threads."""
+    h = rng.standard_normal((n, 8))
+    workers = min(16, os.cpu_count() or 1)
+    if n < _PARALLEL_MIN or workers < 2:
+        return _expi_herm(h, eps)
+    import concurrent.futures
+    chunks = np.array_split(h, workers * 4)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        parts = list(ex.map(lambda c: _expi_herm(c, eps), chunks))
+    return np.concatenate(parts)
 
 
 def sf_boundary_links(l: int) -> tuple[np.ndarray, np.ndarray]:

@@ -1,0 +1,166 @@
+"""GPU parity of the learned preconditioner and its flexible GMRES solve:
+PTC forward against the oracle (same BF16-valued weights), loss and gradient
+of the GPU training kernels against the oracle's analytic gradient, FGMRES
+solutions against the oracle residual, CG fallback on a bad network, and the
+gain of the trained network over GMRES without it."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import native, ptc
+from oracle.dirac import WilsonDirac
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1009_5169_amd as mfq  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def flat(w1, w2):
+    return np.concatenate([w1[:, :, 0].reshape(-1), w2[:, 0, :].reshape(-1)])
+
+
+def unflat(w):
+    w1 = w[: 9 * 8 * 16].reshape(9, 8, 4, 4)[:, :, None]
+    w2 = w[9 * 8 * 16:].reshape(9, 8, 4, 4)[:, None]
+    return w1, w2
+
+
+CASES = [((4, 4, 4, 4), "sf"), ((6, 2, 4, 6), "periodic"), ((4, 6, 2, 4), "antiperiodic")]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[1]}{'x'.join(map(str, c[0]))}")
+def test_ptc_forward_matches_oracle(case):
+    dims, bc = case
+    u = synth.random_links(dims, bc, 0.5, 31)
+    lat = mfq.Lattice(dims, bc, 0.12, to_dev(u))
+    w1, w2 = ptc.init_weights(7, scale=0.3)
+    lat.precond_set_weights(flat(w1, w2))
+    wi1, wi2 = unflat(lat.precond_get_weights("inference"))
+    # the inference weights are the BF16 roundings of the FP32 master weights
+    assert rel(flat(wi1, wi2), flat(w1, w2)) < 5e-3
+    tr = ptc.Transport(WilsonDirac(dims, bc, 0.12, u))
+    r = synth.gaussian_spinors(dims, bc, 3, 32)
+    got = to_host(lat.precond_apply(to_dev(r)))
+    want, _ = ptc.forward(tr, wi1, wi2, r)
+    assert rel(got, want) < 2e-5, rel(got, want)
+    lat.close()
+
+
+def test_ptc_loss_and_gradient_match_oracle():
+    dims, bc = (4, 4, 2, 6), "sf"
+    u = synth.random_links(dims, bc, 0.5, 33)
+    lat = mfq.Lattice(dims, bc, 0.12, to_dev(u))
+    w1, w2 = ptc.init_weights(8, scale=0.3)
+    lat.precond_set_weights(flat(w1, w2))
+    wm1, wm2 = unflat(lat.precond_get_weights("master"))
+    r = synth.gaussian_spinors(dims, bc, 4, 34)
+    e = synth.gaussian_spinors(dims, bc, 4, 35)
+    loss, grad = lat.precond_loss_grad(to_dev(r), to_dev(e))
+    tr = ptc.Transport(WilsonDirac(dims, bc, 0.12, u))
+    loss_ref, g1, g2 = ptc.loss_and_grad(tr, wm1, wm2, r, e)
+    note(f"loss gpu {loss:.8f} oracle {loss_ref:.8f}; grad rel err {rel(grad, flat(g1, g2)):.2e}")
+    assert abs(loss - loss_ref) < 1e-5 * loss_ref
+    assert rel(grad, flat(g1, g2)) < 1e-3
+    lat.close()
+
+
+def _solve_check(lat, d, b, x, tol):
+    x = to_host(x)
+    r = b - d.DdagD(x)
+    for i in range(b.shape[0]):
+        assert np.linalg.norm(r[i]) / np.linalg.norm(b[i]) <= 1.05 * tol
+
+
+@pytest.mark.parametrize("precond", ["identity", "ptc"])
+def test_fgmres_solution_meets_tolerance(precond):
+    dims, bc, kappa = (4, 4, 4, 8), "sf", 0.13
+    u = synth.random_links(dims, bc, 0.3, 1000)
+    lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
+    lat.precond_init(seed=3)
+    b = synth.gaussian_spinors(dims, bc, 3, 2000)
+    x, stats, rc = lat.solve(to_dev(b), tol=1e-10, precond=precond, prec="fp64", max_iter=4000)
+    note(f"fgmres {precond}: rc {rc} iters {[s['iters'] for s in stats]} cycles "
+         f"{[s['reliable_updates'] for s in stats]}")
+    assert rc in (0, 2)
+    _solve_check(lat, native.NativeWilson(dims, bc, kappa, u), b, x, 1e-10)
+    lat.close()
+
+
+def test_bad_network_falls_back_to_cg():
+    dims, bc, kappa = (4, 4, 4, 4), "sf", 0.125
+    u = synth.random_links(dims, bc, 0.3, 1000)
+    lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
+    rng = np.random.default_rng(0)
+    w = (rng.standard_normal(mfq.N_PTC_COMPLEX) + 1j * rng.standard_normal(mfq.N_PTC_COMPLEX)) * 1e3
+    w[: 9 * 8 * 16] = 0.0   # layer 1 maps everything to zero: M = 0
+    lat.precond_set_weights(w)
+    b = synth.gaussian_spinors(dims, bc, 2, 2000)
+    x, stats, rc = lat.solve(to_dev(b), tol=1e-10, precond="ptc", prec="fp64", max_iter=2000)
+    note(f"fallback: rc {rc} stats {stats}")
+    assert rc == 2
+    assert all(s["status"] == 2 for s in stats)
+    _solve_check(lat, native.NativeWilson(dims, bc, kappa, u), b, x, 1e-10)
+    lat.close()
+
+
+def test_pairs_training_and_gain(tmp_path):
+    """Pairs from CG on training RHS, GPU training, and the gain of the trained
+    network: fewer FGMRES iterations than without the network on evaluation RHS
+    disjoint from the training ones."""
+    dims, bc, kappa = (8, 8, 8, 8), "sf", 0.1375
+    u = synth.random_links(dims, bc, 0.5, 1004)
+    d = native.NativeWilson(dims, bc, kappa, u)
+    lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
+    train_b = to_dev(synth.gaussian_spinors(dims, bc, 4, synth.PTC_TRAIN_SEED))
+    r, e = lat.precond_pairs(train_b, every=10, n_snap=4)
+    # the pairs are what CG made: e solves A e = r (to the oracle's FP64 residual)
+    rh, eh = to_host(r), to_host(e)
+    res = np.linalg.norm(rh[:2] - d.DdagD(eh[:2])) / np.linalg.norm(rh[:2])
+    assert res < 1e-9, res
+    lat.precond_init(seed=1)
+    hist = lat.precond_train(r, e, steps=150, lr=3e-3)
+    note(f"training loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    assert hist[-1] < 0.9 * hist[0]
+    path = str(tmp_path / "w.bin")
+    lat.precond_save(path)
+    w_trained = lat.precond_get_weights("master")
+    b = synth.gaussian_spinors(dims, bc, 3, 2400)
+    x_id, st_id, _ = lat.solve(to_dev(b), tol=1e-10, precond="identity", prec="fp64", max_iter=20000)
+    x_pc, st_pc, rc = lat.solve(to_dev(b), tol=1e-10, precond="ptc", prec="fp64", max_iter=20000)
+    lat.precond_init(seed=1)
+    _, st_un, _ = lat.solve(to_dev(b), tol=1e-10, precond="ptc", prec="fp64", max_iter=20000)
+    it_id = [s["iters"] for s in st_id]
+    it_pc = [s["iters"] for s in st_pc]
+    note(f"FGMRES iterations: identity {it_id}, untrained PTC {[s['iters'] for s in st_un]}, trained PTC {it_pc}")
+    assert rc == 0
+    _solve_check(lat, d, b, x_pc, 1e-10)
+    assert sum(it_pc) < sum(it_id)
+    lat.precond_load(path)
+    np.testing.assert_array_equal(lat.precond_get_weights("master"), w_trained)
+    lat.close()

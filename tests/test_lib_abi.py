@@ -42,3 +42,15 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _lib.lib()
+
+
+def test_batch_workload_recipe():
+    """The uneven batch: 64 SF lattices drawn from {8^4, 12^4, 16^3x32}, 1..8
+    RHS each, kappa in [0.12, 0.135]."""
+    import synth
+    probs = synth.batch_problems()
+    assert len(probs) == 64
+    assert {p.dims for p in probs} <= {(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32)}
+    assert len({p.dims for p in probs}) == 3
+    assert all(1 <= p.n_rhs <= 8 and 0.12 <= p.kappa <= 0.135 and p.bc == "sf" for p in probs)
+    assert len({p.link_seed for p in probs}) == 64
