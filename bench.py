@@ -92,16 +92,18 @@ def main():
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # dominant kernel: the fused half-dslash (D epilogue) of the inner CG, same
-    # launch shape as in the solve, timed with HIP events on its stream
+    # dominant kernel: the fused hopping kernel with the D epilogue of the inner
+    # CG (both parities in one launch), same launch shape as in the solve,
+    # timed with HIP events on its stream
     n = p.n_rhs
     hop_ms = lat.time_hop(args.prec, n, iters=200)
-    vh = p.dims[0] * p.dims[1] * p.dims[2] * (p.dims[3] - 1) // 2
-    per_launch = hop_bytes_per_site_rhs(args.prec, n) * vh * n
+    vd = p.dims[0] * p.dims[1] * p.dims[2] * (p.dims[3] - 1)
+    per_launch = hop_bytes_per_site_rhs(args.prec, n) * vd * n
     achieved = per_launch / (hop_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": f"hop_kernel<EPI_D,{args.prec}>", "launch_us": round(hop_ms * 1e3, 3),
+                "kernel": f"hop_kernel<EPI_D,{args.prec}> (both parities)", "launch_us": round(hop_ms * 1e3, 3),
+                "shape": list(lat.hop_shape(args.prec, n)),
                 "algorithmic_bytes_per_launch": int(per_launch)}
 
     # solve-only times on the same GPU: this precision and plain FP64 CG
@@ -151,13 +153,14 @@ def main():
         big = mfq.Lattice(dims, "periodic", 0.12, torch.from_numpy(ub).to(dev))
         del ub
         bw = {}
-        vhb = dims[0] * dims[1] * dims[2] * dims[3] // 2
+        vdb = dims[0] * dims[1] * dims[2] * dims[3]
         for prec in ("fp64", "fp32", "fp16"):
             for nr in (1, 5):
                 ms = big.time_hop(prec, nr, iters=20)
-                gbs = hop_bytes_per_site_rhs(prec, nr) * vhb * nr / (ms * 1e-3) / 1e9
+                gbs = hop_bytes_per_site_rhs(prec, nr) * vdb * nr / (ms * 1e-3) / 1e9
                 bw[f"{prec}_n{nr}"] = {"us": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
-                                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                                       "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                       "shape": list(big.hop_shape(prec, nr))}
                 print(f"[bench] bw {prec} n={nr}: {gbs:.1f} GB/s", file=sys.stderr, flush=True)
         out["dslash_bandwidth"] = {"dims": list(dims), "bc": "periodic",
                                    "kernel": "hop_kernel<EPI_D>", "runs": bw}

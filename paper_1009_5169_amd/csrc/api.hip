@@ -155,19 +155,15 @@ int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field
     }
     case MFQ_OP_HOP:
     case MFQ_OP_HOP_DAG:
-      HIPCHK(run(EPI_HOP, in, out, 0, op == MFQ_OP_HOP_DAG, 1.0));
-      HIPCHK(run(EPI_HOP, in, out, 1, op == MFQ_OP_HOP_DAG, 1.0));
+      HIPCHK(run(EPI_HOP, in, out, 2, op == MFQ_OP_HOP_DAG, 1.0));
       return MFQ_OK;
     case MFQ_OP_D:
     case MFQ_OP_DDAG:
-      HIPCHK(run(EPI_D, in, out, 0, op == MFQ_OP_DDAG, mk));
-      HIPCHK(run(EPI_D, in, out, 1, op == MFQ_OP_DDAG, mk));
+      HIPCHK(run(EPI_D, in, out, 2, op == MFQ_OP_DDAG, mk));
       return MFQ_OK;
     case MFQ_OP_DDAGD:
-      HIPCHK(run(EPI_D, in, tmp, 0, 0, mk));
-      HIPCHK(run(EPI_D, in, tmp, 1, 0, mk));
-      HIPCHK(run(EPI_D, tmp, out, 0, 1, mk));
-      HIPCHK(run(EPI_D, tmp, out, 1, 1, mk));
+      HIPCHK(run(EPI_D, in, tmp, 2, 0, mk));
+      HIPCHK(run(EPI_D, tmp, out, 2, 1, mk));
       return MFQ_OK;
     default:
       return fail(MFQ_ERR_ARG, "unknown operator");
@@ -226,6 +222,7 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
   a.in = a.self = src;
   a.out = dst;
   a.coef = -h->lat.kappa;
+  a.par = 2;
   a.part = part_slot(h, 3);
   float best = 1e30f;
   Shape best_sh = *out;
@@ -286,7 +283,6 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   const double mk = -h->lat.kappa;
   const double tol2 = P->tol * P->tol;
   const double delta2 = delta * delta;
-  const int nb_half = (g.vh + sh.sb - 1) / sh.sb;
   const int nb_full = (2 * g.vh + sh.sb - 1) / sh.sb;
   CgScalars* sc = (CgScalars*)w.sc.ptr;
   Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), r64 = w.r64.view(g), t64 = w.t64.view(g);
@@ -308,34 +304,37 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   a64.coef = mk;
 
   int rc_ = MFQ_OK;
+  // Both parities per launch: the D half reads only p, the D^+ half only t.
+  // On small lattices alpha is reduced inside the update kernel (one launch
+  // fewer); larger ones use the finishing kernel.
+  const int nb2 = (2 * g.vh + sh.sb - 1) / sh.sb;
+  const bool fuse_alpha = nb2 <= 256;
   auto iteration = [&](hipStream_t st) -> int {
-    // t = D p (both parities), partial |t|^2 = p^+ D^+ D p
+    // t = D p, partial |t|^2 = p^+ D^+ D p
     a.in = a.self = in.p;
     a.out = in.t;
     a.dagger = 0;
     a.skip_state = ST_CHECK;
-    a.par = 0;
+    a.par = 2;
     a.part = part_slot(h, 0);
+    a.apart = nullptr;
     HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
-    a.par = 1;
-    a.part = part_slot(h, 1);
-    HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
-    Partials pa[2] = {{part_slot(h, 0), nb_half}, {part_slot(h, 1), nb_half}};
-    HIPCHK(launch_finish(FIN_ALPHA, pa, 2, n, sc, nullptr, tol2, delta2, st));
+    if (!fuse_alpha) {
+      Partials pa{part_slot(h, 0), nb2};
+      HIPCHK(launch_finish(FIN_ALPHA, &pa, 1, n, sc, nullptr, tol2, delta2, st));
+    }
     // Ap = D^+ t; r -= alpha Ap; x += alpha p; partial |r|^2
     a.in = a.self = in.t;
     a.out = in.r;
     a.x = in.x;
     a.p = in.p;
     a.dagger = 1;
-    a.par = 0;
     a.part = part_slot(h, 2);
+    a.apart = fuse_alpha ? part_slot(h, 0) : nullptr;
+    a.anblk = nb2;
     HIPCHK(launch_hop<S, SX>(EPI_CGUPD, a, sh, st));
-    a.par = 1;
-    a.part = part_slot(h, 3);
-    HIPCHK(launch_hop<S, SX>(EPI_CGUPD, a, sh, st));
-    Partials pb[2] = {{part_slot(h, 2), nb_half}, {part_slot(h, 3), nb_half}};
-    HIPCHK(launch_finish(FIN_BETA, pb, 2, n, sc, nullptr, tol2, delta2, st));
+    Partials pb{part_slot(h, 2), nb2};
+    HIPCHK(launch_finish(FIN_BETA, &pb, 1, n, sc, nullptr, tol2, delta2, st));
     HIPCHK(launch_xpay_p<S>(g, in.r, in.p, sc, n, sh, st));
     return MFQ_OK;
   };
@@ -349,22 +348,16 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     a64.out = t64;
     a64.dagger = 0;
     a64.part = nullptr;
-    a64.par = 0;
-    HIPCHK(launch_hop<double, double>(EPI_D, a64, sh, st));
-    a64.par = 1;
+    a64.par = 2;
     HIPCHK(launch_hop<double, double>(EPI_D, a64, sh, st));
     a64.in = a64.self = t64;
     a64.bvec = b64;
     a64.r64 = r64;
     a64.dagger = 1;
-    a64.par = 0;
     a64.part = part_slot(h, 0);
     HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh, st));
-    a64.par = 1;
-    a64.part = part_slot(h, 1);
-    HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh, st));
-    Partials pt[2] = {{part_slot(h, 0), nb_half}, {part_slot(h, 1), nb_half}};
-    HIPCHK(launch_finish(FIN_TRUE, pt, 2, n, sc, nullptr, tol2, delta2, st));
+    Partials pt{part_slot(h, 0), nb2};
+    HIPCHK(launch_finish(FIN_TRUE, &pt, 1, n, sc, nullptr, tol2, delta2, st));
     HIPCHK(launch_restart<S>(g, r64, in.r, in.p, set_p_on_update, sc, n, sh, st));
     return MFQ_OK;
   };
@@ -378,6 +371,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
       return MFQ_OK;
     }
     std::vector<uintptr_t> key = {(uintptr_t)sizeof(S), (uintptr_t)sizeof(SX), (uintptr_t)n, (uintptr_t)k,
+                                  (uintptr_t)fuse_alpha,
                                   (uintptr_t)in.r.data, (uintptr_t)in.p.data, (uintptr_t)in.t.data,
                                   (uintptr_t)in.x.data, (uintptr_t)in.L.data, (uintptr_t)w.part.ptr,
                                   (uintptr_t)sc, bits(tol2), bits(delta2), (uintptr_t)sh.sb,
@@ -412,6 +406,10 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   std::vector<double> rho_prev(n, 0.0);
   int total = 0;
   int rc;
+  // every reliable update follows at least one iteration of some RHS, except
+  // right after a restart: bound them so that the loop always ends
+  int n_updates = 0;
+  const int max_updates = 2 * P->max_iter + 16;
   for (;;) {
     HIPCHK(hipMemcpyAsync(w.host_sc, sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -434,6 +432,12 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
       rho_prev[r] = s.state == ST_ACTIVE ? s.rho : 0.0;
     }
     if (all_done) break;
+    if (need_update && ++n_updates > max_updates) {
+      // reliable updates without iteration progress: stop (bounded loop)
+      HIPCHK(hipMemcpyAsync(w.host_sc, sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      break;
+    }
     if (need_update) {
       if ((rc = reliable_update()) != MFQ_OK) return rc;
       for (int r = 0; r < n; ++r) rho_prev[r] = 0.0;
@@ -678,9 +682,7 @@ int mfq_fermion_force(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq
   a.out = X;
   a.dagger = 1;
   a.coef = -h->lat.kappa;
-  a.par = 0;
-  HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-  a.par = 1;
+  a.par = 2;
   HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
   const size_t force_bytes = (size_t)4 * h->n_slices * g.lx * g.ly * g.lz * 9 * sizeof(d2);
   HIPCHK(hipMemsetAsync(force_dev, 0, force_bytes, st));
@@ -733,6 +735,7 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
     a.in = a.self = w.pd.view(g);
     a.out = w.td.view(g);
     a.coef = -h->lat.kappa;
+    a.par = 2;
     a.part = part_slot(h, 0);
     return timed([&]() { return launch_hop<double, double>(EPI_D, a, sh, st); });
   } else if (prec == MFQ_PREC_FP32_RELIABLE) {
@@ -744,6 +747,7 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
     a.in = a.self = w.ps.view(g);
     a.out = w.ts.view(g);
     a.coef = -h->lat.kappa;
+    a.par = 2;
     a.part = part_slot(h, 0);
     return timed([&]() { return launch_hop<float, float>(EPI_D, a, sh, st); });
   } else {
@@ -756,6 +760,7 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
     a.in = a.self = w.ph.view(g);
     a.out = w.th.view(g);
     a.coef = -h->lat.kappa;
+    a.par = 2;
     a.part = part_slot(h, 0);
     return timed([&]() { return launch_hop<_Float16, float>(EPI_D, a, sh, st); });
   }

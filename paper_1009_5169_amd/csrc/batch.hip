@@ -79,15 +79,13 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat
     const int r = tl.rgrp * L.nr + row;
     double red = 0.0;
     if constexpr (MODE == BM_D || MODE == BM_CG) {
-      HopArgs<S, SX> a = MODE == BM_D ? L.d : L.cg;
-      a.par = par;
+      const HopArgs<S, SX>& a = MODE == BM_D ? L.d : L.cg;
       if (s < a.g.vh && r < a.n_rhs && a.sc[r].state < a.skip_state)
-        red = hop_site<MODE == BM_D ? EPI_D : EPI_CGUPD>(a, s, r);
+        red = hop_site<MODE == BM_D ? EPI_D : EPI_CGUPD>(a, par, s, r, a.sc[r].alpha);
     } else {
-      HopArgs<double, double> a = MODE == BM_D64 ? L.d64 : L.res;
-      a.par = par;
+      const HopArgs<double, double>& a = MODE == BM_D64 ? L.d64 : L.res;
       if (s < a.g.vh && r < a.n_rhs && a.sc[r].state < a.skip_state)
-        red = hop_site<MODE == BM_D64 ? EPI_D : EPI_RES>(a, s, r);
+        red = hop_site<MODE == BM_D64 ? EPI_D : EPI_RES>(a, par, s, r, 0.0);
     }
     if (slot >= 0) tile_partial(red, L.part[slot + par], L.n_rhs, tl.rgrp * L.nr, L.sb, tl.tile, L.nblk_half);
   }
@@ -489,6 +487,10 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
   const int max_k = P->check_every > 0 ? P->check_every : 64;
   const int min_k = max_k < 4 ? max_k : 4;
   int k = min_k, total = 0, rc;
+  // every reliable update follows at least one iteration of some RHS, except
+  // right after a restart: bound them so that the loop always ends
+  int n_updates = 0;
+  const int max_updates = 2 * P->max_iter + 16;
   std::vector<double> rho_prev(B->total, 0.0);
   for (;;) {
     HIPCHK(hipMemcpyAsync(B->host_sc, sc, sizeof(CgScalars) * B->total, hipMemcpyDeviceToHost, st));
@@ -511,6 +513,12 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
       rho_prev[r] = s.state == ST_ACTIVE ? s.rho : 0.0;
     }
     if (all_done) break;
+    if (need_update && ++n_updates > max_updates) {
+      // reliable updates without iteration progress: stop (bounded loop)
+      HIPCHK(hipMemcpyAsync(B->host_sc, sc, sizeof(CgScalars) * B->total, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      break;
+    }
     if (need_update) {
       if ((rc = reliable_update())) return rc;
       for (auto& v : rho_prev) v = 0.0;

@@ -351,17 +351,12 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
     a.out = t64;
     a.dagger = 0;
     a.part = nullptr;
-    for (int par = 0; par < 2; ++par) {
-      a.par = par;
-      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-    }
+    a.par = 2;
+    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
     a.in = a.self = t64;
     a.out = out;
     a.dagger = 1;
-    for (int par = 0; par < 2; ++par) {
-      a.par = par;
-      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-    }
+    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
     return MFQ_OK;
   };
   auto norm_finish = [&](Field<double> f, int j, int which) -> int {
@@ -404,18 +399,14 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
     a.in = a.self = x64;
     a.out = t64;
     a.dagger = 0;
-    for (int par = 0; par < 2; ++par) {
-      a.par = par;
-      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-    }
+    a.par = 2;
+    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
     a.in = a.self = t64;
     a.bvec = b64;
     a.r64 = r64;
     a.dagger = 1;
-    for (int par = 0; par < 2; ++par) {
-      a.par = par;
-      HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
-    }
+    a.par = 2;
+    HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
     if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
     hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, r64, vj(V, 0), n, S);
     HIPCHK(hipMemcpyAsync(host.data(), S, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
@@ -476,18 +467,14 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
     a.out = t64;
     a.dagger = 0;
     a.part = nullptr;
-    for (int par = 0; par < 2; ++par) {
-      a.par = par;
-      HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-    }
+    a.par = 2;
+    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
     a.in = a.self = t64;
     a.bvec = b64;
     a.r64 = r64;
     a.dagger = 1;
-    for (int par = 0; par < 2; ++par) {
-      a.par = par;
-      HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
-    }
+    a.par = 2;
+    HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
     if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
     HIPCHK(hipMemcpyAsync(host.data(), S, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
     status = MFQ_FELL_BACK;

@@ -27,13 +27,51 @@ __device__ __forceinline__ int tile_index(int remap) {
   return xcd * q + (xcd < rem ? xcd : rem) + (b >> 3);
 }
 
+// The CG step length for RHS row threadIdx.y: from the scalars, or, when the
+// |D p|^2 partials are passed (small lattices), reduced here by the row's
+// first wavefront in the same fixed order as the finishing kernel.  On a
+// breakdown (p^+ A p <= 0) alpha is 0 in every workgroup and workgroup 0
+// marks the RHS for a true-residual check.
+template <typename S, typename SX>
+__device__ __forceinline__ double cg_alpha(const HopArgs<S, SX>& a, int r) {
+  if (!a.apart) return r < a.n_rhs ? a.sc[r].alpha : 0.0;
+  __shared__ double s_alpha[8];
+  if (threadIdx.x < 64) {
+    double v = 0.0;
+    if (r < a.n_rhs)
+      for (int j = threadIdx.x; j < a.anblk; j += 64) v += a.apart[(long)r * a.anblk + j];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) {
+      double al = 0.0;
+      if (r < a.n_rhs && a.sc[r].state == ST_ACTIVE) {
+        if (isfinite(v) && v > 0.0) {
+          al = a.sc[r].rho / v;
+        } else if (blockIdx.x == 0) {
+          a.sc[r].state = ST_CHECK;
+        }
+      }
+      s_alpha[threadIdx.y] = al;
+    }
+  }
+  __syncthreads();
+  return s_alpha[threadIdx.y];
+}
+
 template <int EPI, typename S, typename SX>
 __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
-  const int s = tile_index(a.xcd) * blockDim.x + threadIdx.x;
+  int s = tile_index(a.xcd) * blockDim.x + threadIdx.x;
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
-  bool active = s < a.g.vh && r < a.n_rhs;
+  int par = a.par;
+  const int nsites = par == 2 ? 2 * a.g.vh : a.g.vh;
+  double alpha = 0.0;
+  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r);
+  bool active = s < nsites && r < a.n_rhs;
+  if (par == 2) {
+    par = s >= a.g.vh ? 1 : 0;
+    s -= par * a.g.vh;
+  }
   if (active && a.sc) active = a.sc[r].state < a.skip_state;
-  const double red = active ? hop_site<EPI>(a, s, r) : 0.0;
+  const double red = active ? hop_site<EPI>(a, par, s, r, alpha) : 0.0;
   if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
 }
 
@@ -58,7 +96,8 @@ int blocks_for(const Geom&, Shape sh, int n_sites) { return (n_sites + sh.sb - 1
 template <typename S, typename SX>
 hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st) {
   dim3 block(sh.sb, sh.nr);
-  dim3 grid((a.g.vh + sh.sb - 1) / sh.sb, (a.n_rhs + sh.nr - 1) / sh.nr);
+  const int nsites = a.par == 2 ? 2 * a.g.vh : a.g.vh;
+  dim3 grid((nsites + sh.sb - 1) / sh.sb, (a.n_rhs + sh.nr - 1) / sh.nr);
   HopArgs<S, SX> b = a;
   b.xcd = sh.xcd;
   switch (epi) {

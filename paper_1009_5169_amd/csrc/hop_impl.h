@@ -56,10 +56,10 @@ __device__ __forceinline__ void block_partial(double v, double* part, int n_rhs,
 // backward hop from n-mu through U_mu(n-mu)^+.  sgf / sgb are the projector
 // signs (-1 / +1 for H, +1 / -1 for H^+).
 template <int MU, typename S, typename SX, typename T>
-__device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Coords& c, int s, int r,
+__device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, int par, const Coords& c, int s, int r,
                                         T sgf, T sgb, Spinor<T>& acc) {
   const Geom& g = a.g;
-  const int po = 1 - a.par;
+  const int po = 1 - par;
   {  // forward
     int x = c.x, y = c.y, z = c.z, t = c.t;
     T sgn = (T)1;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Coords& c
       Spinor<T> nb;
       load_spinor(a.in, r, po, half_index(g, x, y, z, t), nb);
       cpx<T> u[9];
-      load_link(a.links, a.par, MU, s, u);
+      load_link(a.links, par, MU, s, u);
       cpx<T> h0[3], h1[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) project<MU>(nb, sgf, k, h0[k], h1[k]);
@@ -147,6 +147,7 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
       }
       break;
     case FIN_BETA:
+      s.rp = 0;
       if (s.state == ST_ACTIVE) {
         s.beta = sum / s.rho;
         s.rho = sum;
@@ -186,42 +187,42 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
 }
 
 
-// The hopping term at output site s (parity a.par) for RHS r, followed by the
-// epilogue; returns the value this site contributes to the partial sum.
+// The hopping term at output site s of parity par for RHS r, followed by the
+// epilogue (alpha is the CG step length, used by EPI_CGUPD); returns the value
+// this site contributes to the partial sum.
 template <int EPI, typename S, typename SX>
-__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int s, int r) {
+__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int s, int r, double al) {
   using T = typename Compute<S>::T;
   double red = 0.0;
   Spinor<T> acc;
   zero(acc);
-  const Coords c = site_coords(a.g, s, a.par);
+  const Coords c = site_coords(a.g, s, par);
   const T sgf = a.dagger ? (T)1 : (T)-1;
   const T sgb = -sgf;
-  hop_dir<0>(a, c, s, r, sgf, sgb, acc);
-  hop_dir<1>(a, c, s, r, sgf, sgb, acc);
-  hop_dir<2>(a, c, s, r, sgf, sgb, acc);
-  hop_dir<3>(a, c, s, r, sgf, sgb, acc);
+  hop_dir<0>(a, par, c, s, r, sgf, sgb, acc);
+  hop_dir<1>(a, par, c, s, r, sgf, sgb, acc);
+  hop_dir<2>(a, par, c, s, r, sgf, sgb, acc);
+  hop_dir<3>(a, par, c, s, r, sgf, sgb, acc);
   const T b = (T)a.coef;
   if constexpr (EPI == EPI_HOP) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc.v[k] = b * acc.v[k];
-    store_spinor(a.out, r, a.par, s, acc);
+    store_spinor(a.out, r, par, s, acc);
   } else if constexpr (EPI == EPI_D) {
     Spinor<T> self;
-    load_spinor(a.self, r, a.par, s, self);
+    load_spinor(a.self, r, par, s, self);
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc.v[k] = self.v[k] + b * acc.v[k];
-    store_spinor(a.out, r, a.par, s, acc);
+    store_spinor(a.out, r, par, s, acc);
     red = snorm2(acc);
   } else if constexpr (EPI == EPI_CGUPD) {
     using TX = typename Compute<SX>::T;
     Spinor<T> self, rr, pp;
     Spinor<TX> xx;
-    load_spinor(a.self, r, a.par, s, self);
-    load_spinor(a.out, r, a.par, s, rr);
-    load_spinor(a.p, r, a.par, s, pp);
-    load_spinor(a.x, r, a.par, s, xx);
-    const double al = a.sc[r].alpha;
+    load_spinor(a.self, r, par, s, self);
+    load_spinor(a.out, r, par, s, rr);
+    load_spinor(a.p, r, par, s, pp);
+    load_spinor(a.x, r, par, s, xx);
     const T alpha = (T)al;
     const TX alx = (TX)al;
 #pragma unroll
@@ -230,20 +231,20 @@ __device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int s, int r
       rr.v[k] = rr.v[k] - alpha * ap;
       xx.v[k] = xx.v[k] + alx * cpx<TX>{(TX)pp.v[k].re, (TX)pp.v[k].im};
     }
-    store_spinor(a.out, r, a.par, s, rr);
-    store_spinor(a.x, r, a.par, s, xx);
+    store_spinor(a.out, r, par, s, rr);
+    store_spinor(a.x, r, par, s, xx);
     red = snorm2(rr);
   } else {  // EPI_RES (FP64)
     Spinor<double> self, bb;
-    load_spinor(a.self, r, a.par, s, self);
-    load_spinor(a.bvec, r, a.par, s, bb);
+    load_spinor(a.self, r, par, s, self);
+    load_spinor(a.bvec, r, par, s, bb);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const cpx<double> ap = {(double)self.v[k].re + (double)b * (double)acc.v[k].re,
                               (double)self.v[k].im + (double)b * (double)acc.v[k].im};
       bb.v[k] = bb.v[k] - ap;
     }
-    store_spinor(a.r64, r, a.par, s, bb);
+    store_spinor(a.r64, r, par, s, bb);
     red = snorm2(bb);
   }
   return red;

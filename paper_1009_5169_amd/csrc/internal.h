@@ -75,9 +75,12 @@ struct HopArgs {
   Field<S> p;          // EPI_CGUPD search direction
   Field<double> bvec;  // EPI_RES right-hand side
   Field<double> r64;   // EPI_RES output
-  const CgScalars* sc; // per-RHS scalars (alpha, state) or null
+  CgScalars* sc;       // per-RHS scalars (alpha, state) or null
   double* part;        // partial sums [n_rhs][gridDim.x] or null
-  int par, n_rhs, dagger, skip_state;
+  const double* apart; // EPI_CGUPD: reduce alpha from these |D p|^2 partials [n_rhs][anblk]
+  int anblk;
+  int par;             // output parity 0 / 1, or 2 for both parities in one launch
+  int n_rhs, dagger, skip_state;
   int xcd;             // set by the launcher from the Shape
   double coef;         // coefficient of the hopping term
 };
