@@ -27,18 +27,20 @@ HBM_PEAK_GBS = 8000.0
 
 
 def hop_bytes_per_site_rhs(prec: str, n_rhs: int) -> float:
-    """Algorithmic HBM bytes of the fused half-dslash D-epilogue kernel per
-    output site per RHS: the other-parity input read once, the same-parity
-    input read once, the output written once, and the 8 links of the site
-    (each link is read once per launch) shared by the n_rhs RHS.  FP64 links
-    are 18 reals; the FP32 / FP16 copies store two rows (12 reals)."""
+    """Algorithmic HBM bytes of the timed hopping kernel (D epilogue, both
+    parities in one launch, input = self field) per lattice site per RHS: the
+    input spinor read once, the output written once, and the site's 4 links
+    U_mu(n) read once per launch and shared by the n_rhs RHS (every link is
+    the forward link of one site and the backward link of its neighbour).
+    FP64 links are 18 reals; the FP32 / FP16 copies store two rows (12 reals);
+    FP16 spinors carry one FP32 norm."""
     if prec == "fp64":
         spinor, link = 24 * 8, 18 * 8
     elif prec == "fp32":
         spinor, link = 24 * 4, 12 * 4
     else:  # fp16 values + one fp32 norm per site
         spinor, link = 24 * 2 + 4, 12 * 2
-    return 3 * spinor + 8 * link / n_rhs
+    return 2 * spinor + 4 * link / n_rhs
 
 
 def main():
@@ -228,8 +230,9 @@ def bench_fp16(synth, mfq, torch, dev, np):
 
 def bench_learned(synth, mfq, torch, dev, np):
     """16^3x16 SF, eps = 0.5, kappa = 0.1375, 5 evaluation RHS: train the PTC
-    network on CG pairs from training RHS (seeds 6000+), then FGMRES(16) with
-    it, FGMRES(16) without it and plain FP64 CG, all to 1e-10."""
+    network on pairs from plain CG on b = A xi with known Gaussian solutions xi
+    (seeds 6000+), then FGMRES(16) with it, FGMRES(16) without it and plain
+    FP64 CG, all to 1e-10."""
     p = synth.CONFIG_4
     print(f"[bench] row learned {p.name}", file=sys.stderr, flush=True)
     lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
@@ -237,7 +240,7 @@ def bench_learned(synth, mfq, torch, dev, np):
     tb = torch.from_numpy(synth.gaussian_spinors(p.dims, p.bc, 4, synth.PTC_TRAIN_SEED)).to(dev)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    r, e = lat.precond_pairs(tb, every=25, n_snap=4)
+    r, e = lat.precond_pairs(tb, every=5, n_snap=4)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t
     lat.precond_init(seed=1)

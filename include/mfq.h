@@ -215,11 +215,15 @@ int mfq_precond_loss_grad(mfq_handle* h, const double* r_dev, const double* e_de
  * loss_hist_host[steps] (may be NULL). */
 int mfq_precond_train(mfq_handle* h, const double* r_dev, const double* e_dev, int n_pairs, int steps, double lr,
                       double* loss_hist_host, void* stream);
-/* Training pairs from plain FP64 CG on the n_rhs right-hand sides b: for
- * j = 1..n_snap the iterate x_k after k = every * j iterations gives
- * r = (b - A x_k) / |b - A x_k| and e = (x* - x_k) / |b - A x_k|, x* the
- * converged solution.  r_out, e_out: n_snap * n_rhs spinors, pair j-major. */
-int mfq_precond_pairs(mfq_handle* h, const double* b_dev, int n_rhs, int every, int n_snap, double* r_out,
+/* Training pairs from plain FP64 CG with a known solution: for the n_rhs
+ * canonical spinors xi (device, FP64) CG runs on b = A xi from x_0 = 0, and
+ * for j = 0..n_snap-1 its iterate x_k after k = every * j iterations gives
+ * r = (b - A x_k) / |b - A x_k| and e = (xi - x_k) / |b - A x_k|, so that
+ * A e = r.  The pair at k = 0 is (A xi, xi) / |A xi|: its error is spread
+ * over the whole spectrum, the later ones lean to the low modes.  r_out,
+ * e_out: n_snap * n_rhs canonical spinors each (device), pair j-major.
+ * xi must be nonzero and finite (MFQ_ERR_ARG otherwise). */
+int mfq_precond_pairs(mfq_handle* h, const double* xi_dev, int n_rhs, int every, int n_snap, double* r_out,
                       double* e_out, void* stream);
 int mfq_precond_save(mfq_handle* h, const char* path);
 int mfq_precond_load(mfq_handle* h, const char* path);

@@ -85,7 +85,7 @@ class Lattice:
         stats = (SolveStats * n)()
         rc = _lib.lib().mfq_solve_multi_rhs(self._h, _lib.dptr(b), _lib.dptr(x), n, ctypes.byref(p),
                                             stats, _lib.stream_ptr(stream))
-        _lib.check(rc, allow=(0, 1))
+        _lib.check(rc, allow=(0, 1, 2))
         return x, [s.as_dict() for s in stats], rc
 
     def force(self, phi: torch.Tensor, params=None, want_xy: bool = False, stream=None, **kw):
@@ -101,7 +101,7 @@ class Lattice:
             self._h, _lib.dptr(phi), n, ctypes.byref(p), _lib.dptr(g), action,
             _lib.dptr(x) if want_xy else None, _lib.dptr(y) if want_xy else None, stats,
             _lib.stream_ptr(stream))
-        _lib.check(rc, allow=(0, 1))
+        _lib.check(rc, allow=(0, 1, 2))
         out = (g, list(action), [s.as_dict() for s in stats], rc)
         return out + (x, y) if want_xy else out
 
@@ -145,7 +145,8 @@ class Batch:
         """bs: list of canonical spinor tensors; returns (xs, stats per lattice, status)."""
         if len(bs) != len(self.lattices):
             raise ValueError("one right-hand-side tensor per lattice")
-        p = params if params is not None else make_params(prec=self.prec, **kw)
+        kw.setdefault("prec", self.prec)
+        p = params if params is not None else make_params(**kw)
         for lat, b, n in zip(self.lattices, bs, self.n_rhs):
             if lat._check_spinor(b) != n:
                 raise ValueError("RHS count differs from the batch's")
@@ -230,13 +231,14 @@ def _precond_train(self, r: torch.Tensor, e: torch.Tensor, steps: int = 100, lr:
     return hist
 
 
-def _precond_pairs(self, b: torch.Tensor, every: int, n_snap: int, stream=None):
-    """(r, e) training pairs from plain CG on b: n_snap * n_rhs spinors each."""
-    n = self._check_spinor(b)
+def _precond_pairs(self, xi: torch.Tensor, every: int, n_snap: int, stream=None):
+    """(r, e) training pairs from plain CG on b = A xi with the known solution
+    xi, at k = every * j iterations for j = 0..n_snap-1: n_snap * n_rhs spinors each."""
+    n = self._check_spinor(xi)
     shape = self.spinor_shape(n * n_snap)
-    r = torch.empty(shape, dtype=torch.complex128, device=b.device)
-    e = torch.empty(shape, dtype=torch.complex128, device=b.device)
-    _lib.check(_lib.lib().mfq_precond_pairs(self._h, _lib.dptr(b), n, int(every), int(n_snap), _lib.dptr(r),
+    r = torch.empty(shape, dtype=torch.complex128, device=xi.device)
+    e = torch.empty(shape, dtype=torch.complex128, device=xi.device)
+    _lib.check(_lib.lib().mfq_precond_pairs(self._h, _lib.dptr(xi), n, int(every), int(n_snap), _lib.dptr(r),
                                             _lib.dptr(e), _lib.stream_ptr(stream)))
     return r, e
 

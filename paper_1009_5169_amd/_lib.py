@@ -128,6 +128,8 @@ def lib():
 def check(code: int, allow=(MFQ_OK,)) -> int:
     if code in allow:
         return code
+    if code > 0:  # a status, not an error: the last error message is unrelated
+        raise MfqError(code, "unexpected status")
     msg = lib().mfq_last_error()
     raise MfqError(code, msg.decode() if msg else "")
 

@@ -273,8 +273,8 @@ struct Stat {
 // The inner recursion runs in storage S; the solution correction in SX.  Every
 // RHS has its own scalars; converged RHS are masked out of the vector work.
 template <typename S, typename SX>
-int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> in, int set_p_on_update,
-           double delta, hipStream_t st, mfq_solve_stats* stats) {
+int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> in, double delta, hipStream_t st,
+           mfq_solve_stats* stats) {
   Workspace& w = h->ws;
   const Geom& g = h->g;
   Shape sh;
@@ -294,7 +294,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, field_chunks<double>(g, n) * sizeof(d2), st));
   HIPCHK(hipMemsetAsync(in.x.data, 0, field_chunks<SX>(g, n) * sizeof(typename Store<SX>::chunk), st));
   if (sizeof(SX) == 2) HIPCHK(hipMemsetAsync(in.x.norm, 0, (size_t)n * 2 * g.vh * sizeof(float), st));
-  HIPCHK(launch_restart<S>(g, r64, in.r, in.p, 1, sc, n, sh, st));
+  HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, sh, st));
 
   HopArgs<S, SX> a = hop_args<S, SX>(h, in.L, n);
   a.sc = sc;
@@ -314,7 +314,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     a.in = a.self = in.p;
     a.out = in.t;
     a.dagger = 0;
-    a.skip_state = ST_CHECK;
+    a.skip_state = ST_WAIT;
     a.par = 2;
     a.part = part_slot(h, 0);
     a.apart = nullptr;
@@ -339,11 +339,12 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     return MFQ_OK;
   };
 
-  // fold the correction into x64, recompute r64 = b - A x64 in FP64, and
-  // restart the inner recursion from it (RHS that meet tol become DONE)
-  auto reliable_update = [&]() -> int {
-    HIPCHK(launch_fold<SX>(g, in.x, x64, sc, n, sh, st));
-    a64.skip_state = ST_DONE;
+  // For the RHS that the update covers (mode): fold the correction into x64,
+  // recompute r64 = b - A x64 in FP64, and continue the inner recursion from
+  // it (RHS that meet tol become DONE).
+  auto reliable_update = [&](int mode) -> int {
+    HIPCHK(launch_fold<SX>(g, in.x, x64, sc, n, mode, sh, st));
+    a64.upd_mode = mode;
     a64.in = a64.self = x64;
     a64.out = t64;
     a64.dagger = 0;
@@ -357,8 +358,8 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     a64.part = part_slot(h, 0);
     HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh, st));
     Partials pt{part_slot(h, 0), nb2};
-    HIPCHK(launch_finish(FIN_TRUE, &pt, 1, n, sc, nullptr, tol2, delta2, st));
-    HIPCHK(launch_restart<S>(g, r64, in.r, in.p, set_p_on_update, sc, n, sh, st));
+    HIPCHK(launch_finish(mode == UPD_ALL ? FIN_TRUE : FIN_TRUE_FLAGGED, &pt, 1, n, sc, nullptr, tol2, delta2, st));
+    HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, sh, st));
     return MFQ_OK;
   };
 
@@ -397,9 +398,10 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     return MFQ_OK;
   };
 
-  // Poll interval: predicted iterations to convergence of the slowest RHS from
-  // the last interval's contraction rate, rounded to a power of two (so only a
-  // few graph sizes exist), within [min_k, max_k].
+  // Poll interval: predicted iterations until the first RHS pauses for a
+  // reliable update or claims convergence, from the last interval's
+  // contraction rate, rounded down to a power of two (so only a few graph
+  // sizes exist), within [min_k, max_k].  A paused RHS idles until the poll.
   const int max_k = P->check_every > 0 ? P->check_every : 64;
   const int min_k = max_k < 4 ? max_k : 4;
   int k = min_k;
@@ -413,13 +415,13 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   for (;;) {
     HIPCHK(hipMemcpyAsync(w.host_sc, sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    bool all_done = true, need_update = false;
+    bool all_done = true, need_update = false, have = false;
     int max_it = 0;
-    double want = 0.0;
+    double want = 1e30;
     for (int r = 0; r < n; ++r) {
       const CgScalars& s = w.host_sc[r];
       all_done = all_done && s.state == ST_DONE;
-      need_update = need_update || s.state == ST_CHECK || s.upd;
+      need_update = need_update || in_update(s, UPD_FLAGGED);
       if (s.state != ST_DONE && s.iters > max_it) max_it = s.iters;
       if (s.state == ST_ACTIVE && rho_prev[r] > 0.0 && s.rho < rho_prev[r] && total > 0) {
         // iterations until rho <= min(tol^2, delta^2 rho_ru) at the observed rate
@@ -427,7 +429,8 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
         double target = tol2 * s.bnorm2;
         if (delta2 > 0.0 && delta2 * s.rho_ru > target) target = delta2 * s.rho_ru;
         const double it = log(target / s.rho) / rate;
-        if (it > want) want = it;
+        if (it < want) want = it;
+        have = true;
       }
       rho_prev[r] = s.state == ST_ACTIVE ? s.rho : 0.0;
     }
@@ -439,20 +442,21 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
       break;
     }
     if (need_update) {
-      if ((rc = reliable_update()) != MFQ_OK) return rc;
-      for (int r = 0; r < n; ++r) rho_prev[r] = 0.0;
+      if ((rc = reliable_update(UPD_FLAGGED)) != MFQ_OK) return rc;
+      for (int r = 0; r < n; ++r)
+        if (in_update(w.host_sc[r], UPD_FLAGGED)) rho_prev[r] = 0.0;
       k = min_k;
       continue;
     }
     if (max_it >= P->max_iter) {
-      if ((rc = reliable_update()) != MFQ_OK) return rc;
+      if ((rc = reliable_update(UPD_ALL)) != MFQ_OK) return rc;
       HIPCHK(hipMemcpyAsync(w.host_sc, sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       break;
     }
-    if (total > 0) {
+    if (have) {
       int kk = min_k;
-      while (kk < max_k && kk * 2 <= (int)(want + 1.0)) kk *= 2;
+      while (kk < max_k && kk * 2 <= (int)(fmin(want, (double)max_k) + 1.0)) kk *= 2;
       k = kk;
     }
     if (k > P->max_iter - max_it) k = P->max_iter - max_it;
@@ -498,7 +502,7 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       HIPCHK(w.td.alloc(g, n));
       InnerFields<double, double> in{links_d(h), w.rd.view(g), w.pd.view(g), w.td.view(g), w.xd.view(g)};
       // FP64: no reliable updates; the true residual is checked at the end
-      return run_cg<double, double>(h, n, P, in, 1, 0.0, st, stats);
+      return run_cg<double, double>(h, n, P, in, 0.0, st, stats);
     }
     case MFQ_PREC_FP32_RELIABLE: {
       HIPCHK(w.xs.alloc(g, n));
@@ -506,7 +510,7 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       HIPCHK(w.ps.alloc(g, n));
       HIPCHK(w.ts.alloc(g, n));
       InnerFields<float, float> in{links_f(h), w.rs.view(g), w.ps.view(g), w.ts.view(g), w.xs.view(g)};
-      return run_cg<float, float>(h, n, P, in, 0, delta, st, stats);
+      return run_cg<float, float>(h, n, P, in, delta, st, stats);
     }
     default: {
       HIPCHK(w.xs.alloc(g, n));
@@ -514,7 +518,7 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       HIPCHK(w.ph.alloc(g, n));
       HIPCHK(w.th.alloc(g, n));
       InnerFields<_Float16, float> in{links_h(h), w.rh.view(g), w.ph.view(g), w.th.view(g), w.xs.view(g)};
-      return run_cg<_Float16, float>(h, n, P, in, 1, delta, st, stats);
+      return run_cg<_Float16, float>(h, n, P, in, delta, st, stats);
     }
   }
 }

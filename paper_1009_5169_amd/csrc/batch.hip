@@ -70,7 +70,7 @@ constexpr int kBatchThreads = 512;
 
 template <int MODE, typename S, typename SX>
 __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat<S, SX>* lats, const Tile* tiles,
-                                                                  int n_tiles, int par, int slot) {
+                                                                  int n_tiles, int par, int slot, int mode) {
   for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
     const Tile tl = tiles[it];
     const BatchLat<S, SX>& L = lats[tl.lat];
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat
         red = hop_site<MODE == BM_D ? EPI_D : EPI_CGUPD>(a, par, s, r, a.sc[r].alpha);
     } else {
       const HopArgs<double, double>& a = MODE == BM_D64 ? L.d64 : L.res;
-      if (s < a.g.vh && r < a.n_rhs && a.sc[r].state < a.skip_state)
+      if (s < a.g.vh && r < a.n_rhs && in_update(a.sc[r], mode))
         red = hop_site<MODE == BM_D64 ? EPI_D : EPI_RES>(a, par, s, r, 0.0);
     }
     if (slot >= 0) tile_partial(red, L.part[slot + par], L.n_rhs, tl.rgrp * L.nr, L.sb, tl.tile, L.nblk_half);
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat
 
 template <int MODE, typename S, typename SX>
 __global__ __launch_bounds__(kBatchThreads) void batch_vec_kernel(const BatchLat<S, SX>* lats, const Tile* tiles,
-                                                                  int n_tiles, int set_p) {
+                                                                  int n_tiles, int mode) {
   using T = typename Compute<S>::T;
   using TX = typename Compute<SX>::T;
   for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_vec_kernel(const BatchLat
         store_spinor(L.p, r, par, s, pp);
       }
     } else if constexpr (MODE == BV_FOLD) {
-      if (valid && L.sc[r].state != ST_DONE) {
+      if (valid && in_update(L.sc[r], mode)) {
         Spinor<TX> a;
         Spinor<double> b;
         load_spinor(L.x, r, par, s, a);
@@ -132,14 +132,24 @@ __global__ __launch_bounds__(kBatchThreads) void batch_vec_kernel(const BatchLat
         store_spinor(L.x, r, par, s, a);
       }
     } else if constexpr (MODE == BV_RESTART) {
-      if (valid && L.sc[r].state == ST_ACTIVE) {
+      if (valid && L.sc[r].state == ST_ACTIVE && L.sc[r].fresh) {
         Spinor<double> a;
         load_spinor(L.r64, r, par, s, a);
         Spinor<T> b;
 #pragma unroll
         for (int k = 0; k < 12; ++k) b.v[k] = {(T)a.v[k].re, (T)a.v[k].im};
         store_spinor(L.r, r, par, s, b);
-        if (set_p || L.sc[r].rp) store_spinor(L.p, r, par, s, b);
+        const int rp = L.sc[r].rp;
+        if (rp == 2) {  // finish the paused step: p = r + beta p
+          const T beta = (T)L.sc[r].beta;
+          Spinor<T> pp;
+          load_spinor(L.p, r, par, s, pp);
+#pragma unroll
+          for (int k = 0; k < 12; ++k) pp.v[k] = b.v[k] + beta * pp.v[k];
+          store_spinor(L.p, r, par, s, pp);
+        } else if (rp == 1) {
+          store_spinor(L.p, r, par, s, b);
+        }
       }
     } else {  // BV_INIT: r64 = b, partial |b|^2
       double v = 0.0;
@@ -295,7 +305,7 @@ int batch_setup(mfq_batch* B) {
     L.d = hop_args<S, SX>(h, Inner<S, SX>::L(h), n);
     L.d.sc = L.sc;
     L.d.coef = mk;
-    L.d.skip_state = ST_CHECK;
+    L.d.skip_state = ST_WAIT;
     L.d.in = L.d.self = L.p;
     L.d.out = Inner<S, SX>::t(h);
     L.cg = L.d;
@@ -346,29 +356,29 @@ int batch_setup(mfq_batch* B) {
 }
 
 template <typename S, typename SX>
-hipError_t bhop(mfq_batch* B, int mode, int par, int slot, hipStream_t st) {
+hipError_t bhop(mfq_batch* B, int mode, int par, int slot, hipStream_t st, int upd_mode = UPD_ALL) {
   const BatchLat<S, SX>* L = (const BatchLat<S, SX>*)B->lats.ptr;
   const Tile* t = (const Tile*)B->tiles_h.ptr;
   const int grid = B->grid < B->n_tiles_h ? B->grid : B->n_tiles_h;
   switch (mode) {
-    case BM_D: hipLaunchKernelGGL((batch_hop_kernel<BM_D, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot); break;
-    case BM_CG: hipLaunchKernelGGL((batch_hop_kernel<BM_CG, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot); break;
-    case BM_D64: hipLaunchKernelGGL((batch_hop_kernel<BM_D64, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot); break;
-    default: hipLaunchKernelGGL((batch_hop_kernel<BM_RES, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot); break;
+    case BM_D: hipLaunchKernelGGL((batch_hop_kernel<BM_D, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
+    case BM_CG: hipLaunchKernelGGL((batch_hop_kernel<BM_CG, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
+    case BM_D64: hipLaunchKernelGGL((batch_hop_kernel<BM_D64, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
+    default: hipLaunchKernelGGL((batch_hop_kernel<BM_RES, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
   }
   return hipGetLastError();
 }
 
 template <typename S, typename SX>
-hipError_t bvec(mfq_batch* B, int mode, int set_p, hipStream_t st) {
+hipError_t bvec(mfq_batch* B, int mode, int arg, hipStream_t st) {
   const BatchLat<S, SX>* L = (const BatchLat<S, SX>*)B->lats.ptr;
   const Tile* t = (const Tile*)B->tiles_f.ptr;
   const int grid = B->grid < B->n_tiles_f ? B->grid : B->n_tiles_f;
   switch (mode) {
-    case BV_XPAY: hipLaunchKernelGGL((batch_vec_kernel<BV_XPAY, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, set_p); break;
-    case BV_FOLD: hipLaunchKernelGGL((batch_vec_kernel<BV_FOLD, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, set_p); break;
-    case BV_RESTART: hipLaunchKernelGGL((batch_vec_kernel<BV_RESTART, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, set_p); break;
-    default: hipLaunchKernelGGL((batch_vec_kernel<BV_INIT, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, set_p); break;
+    case BV_XPAY: hipLaunchKernelGGL((batch_vec_kernel<BV_XPAY, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
+    case BV_FOLD: hipLaunchKernelGGL((batch_vec_kernel<BV_FOLD, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
+    case BV_RESTART: hipLaunchKernelGGL((batch_vec_kernel<BV_RESTART, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
+    default: hipLaunchKernelGGL((batch_vec_kernel<BV_INIT, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
   }
   return hipGetLastError();
 }
@@ -418,7 +428,6 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
   const double tol2 = P->tol * P->tol;
   const double delta = P->prec == MFQ_PREC_FP64 ? 0.0 : (P->reliable_delta > 0.0 ? P->reliable_delta : 0.1);
   const double delta2 = delta * delta;
-  const int set_p_on_update = P->prec == MFQ_PREC_FP32_RELIABLE ? 0 : 1;
   const int n_lat = (int)B->hs.size();
   CgScalars* sc = (CgScalars*)B->sc.ptr;
 
@@ -432,7 +441,7 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
   }
   HIPCHK(bvec<S, SX>(B, BV_INIT, 0, st));
   HIPCHK(bfin(B, FI_INIT, FIN_INIT, tol2, delta2, st));
-  HIPCHK(bvec<S, SX>(B, BV_RESTART, 1, st));
+  HIPCHK(bvec<S, SX>(B, BV_RESTART, 0, st));
 
   auto iteration = [&](hipStream_t s) -> int {
     HIPCHK(bhop<S, SX>(B, BM_D, 0, 0, s));
@@ -444,14 +453,15 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
     HIPCHK(bvec<S, SX>(B, BV_XPAY, 0, s));
     return MFQ_OK;
   };
-  auto reliable_update = [&]() -> int {
-    HIPCHK(bvec<S, SX>(B, BV_FOLD, 0, st));
-    HIPCHK(bhop<S, SX>(B, BM_D64, 0, -1, st));
-    HIPCHK(bhop<S, SX>(B, BM_D64, 1, -1, st));
-    HIPCHK(bhop<S, SX>(B, BM_RES, 0, 0, st));
-    HIPCHK(bhop<S, SX>(B, BM_RES, 1, 0, st));
-    HIPCHK(bfin(B, FI_TRUE, FIN_TRUE, tol2, delta2, st));
-    HIPCHK(bvec<S, SX>(B, BV_RESTART, set_p_on_update, st));
+  // per-RHS reliable update over the RHS the mode covers
+  auto reliable_update = [&](int mode) -> int {
+    HIPCHK(bvec<S, SX>(B, BV_FOLD, mode, st));
+    HIPCHK(bhop<S, SX>(B, BM_D64, 0, -1, st, mode));
+    HIPCHK(bhop<S, SX>(B, BM_D64, 1, -1, st, mode));
+    HIPCHK(bhop<S, SX>(B, BM_RES, 0, 0, st, mode));
+    HIPCHK(bhop<S, SX>(B, BM_RES, 1, 0, st, mode));
+    HIPCHK(bfin(B, FI_TRUE, mode == UPD_ALL ? FIN_TRUE : FIN_TRUE_FLAGGED, tol2, delta2, st));
+    HIPCHK(bvec<S, SX>(B, BV_RESTART, 0, st));
     return MFQ_OK;
   };
   auto run_iters = [&](int k) -> int {
@@ -495,20 +505,21 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
   for (;;) {
     HIPCHK(hipMemcpyAsync(B->host_sc, sc, sizeof(CgScalars) * B->total, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    bool all_done = true, need_update = false;
+    bool all_done = true, need_update = false, have = false;
     int max_it = 0;
-    double want = 0.0;
+    double want = 1e30;
     for (int r = 0; r < B->total; ++r) {
       const CgScalars& s = B->host_sc[r];
       all_done = all_done && s.state == ST_DONE;
-      need_update = need_update || s.state == ST_CHECK || s.upd;
+      need_update = need_update || in_update(s, UPD_FLAGGED);
       if (s.state != ST_DONE && s.iters > max_it) max_it = s.iters;
       if (s.state == ST_ACTIVE && rho_prev[r] > 0.0 && s.rho < rho_prev[r] && total > 0) {
         const double rate = log(s.rho / rho_prev[r]) / k;
         double target = tol2 * s.bnorm2;
         if (delta2 > 0.0 && delta2 * s.rho_ru > target) target = delta2 * s.rho_ru;
         const double it = log(target / s.rho) / rate;
-        if (it > want) want = it;
+        if (it < want) want = it;
+        have = true;
       }
       rho_prev[r] = s.state == ST_ACTIVE ? s.rho : 0.0;
     }
@@ -520,20 +531,21 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
       break;
     }
     if (need_update) {
-      if ((rc = reliable_update())) return rc;
-      for (auto& v : rho_prev) v = 0.0;
+      if ((rc = reliable_update(UPD_FLAGGED))) return rc;
+      for (int r = 0; r < B->total; ++r)
+        if (in_update(B->host_sc[r], UPD_FLAGGED)) rho_prev[r] = 0.0;
       k = min_k;
       continue;
     }
     if (max_it >= P->max_iter) {
-      if ((rc = reliable_update())) return rc;
+      if ((rc = reliable_update(UPD_ALL))) return rc;
       HIPCHK(hipMemcpyAsync(B->host_sc, sc, sizeof(CgScalars) * B->total, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       break;
     }
-    if (total > 0) {
+    if (have) {
       int kk = min_k;
-      while (kk < max_k && kk * 2 <= (int)(want + 1.0)) kk *= 2;
+      while (kk < max_k && kk * 2 <= (int)(fmin(want, (double)max_k) + 1.0)) kk *= 2;
       k = kk;
     }
     if (k > P->max_iter - max_it) k = P->max_iter - max_it;

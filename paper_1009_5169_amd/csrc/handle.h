@@ -96,6 +96,7 @@ HopArgs<S, SX> hop_args(mfq_handle* h, Links<S> L, int n_rhs) {
   a.links = L;
   a.n_rhs = n_rhs;
   a.skip_state = 3;
+  a.upd_mode = -1;
   return a;
 }
 

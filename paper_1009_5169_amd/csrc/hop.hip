@@ -70,7 +70,7 @@ __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
     par = s >= a.g.vh ? 1 : 0;
     s -= par * a.g.vh;
   }
-  if (active && a.sc) active = a.sc[r].state < a.skip_state;
+  if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
   const double red = active ? hop_site<EPI>(a, par, s, r, alpha) : 0.0;
   if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
 }
@@ -193,9 +193,9 @@ __global__ void xpay_p_kernel(Geom g, Field<S> rf, Field<S> pf, const CgScalars*
 }
 
 template <typename SX>
-__global__ void fold_kernel(Geom g, Field<SX> xi, Field<double> x64, const CgScalars* sc, int n_rhs) {
+__global__ void fold_kernel(Geom g, Field<SX> xi, Field<double> x64, const CgScalars* sc, int n_rhs, int mode) {
   MFQ_FULL_LANE
-  if (sc[r].state == ST_DONE) return;
+  if (!in_update(sc[r], mode)) return;
   using TX = typename Compute<SX>::T;
   Spinor<TX> a;
   Spinor<double> b;
@@ -212,10 +212,10 @@ __global__ void fold_kernel(Geom g, Field<SX> xi, Field<double> x64, const CgSca
 }
 
 template <typename S>
-__global__ void restart_kernel(Geom g, Field<double> r64, Field<S> ri, Field<S> pi, int set_p,
-                               const CgScalars* sc, int n_rhs) {
+__global__ void restart_kernel(Geom g, Field<double> r64, Field<S> ri, Field<S> pi, const CgScalars* sc,
+                               int n_rhs) {
   MFQ_FULL_LANE
-  if (sc[r].state != ST_ACTIVE) return;
+  if (sc[r].state != ST_ACTIVE || !sc[r].fresh) return;
   using T = typename Compute<S>::T;
   Spinor<double> a;
   load_spinor(r64, r, par, s, a);
@@ -223,7 +223,17 @@ __global__ void restart_kernel(Geom g, Field<double> r64, Field<S> ri, Field<S> 
 #pragma unroll
   for (int k = 0; k < 12; ++k) b.v[k] = {(T)a.v[k].re, (T)a.v[k].im};
   store_spinor(ri, r, par, s, b);
-  if (set_p || sc[r].rp) store_spinor(pi, r, par, s, b);
+  const int rp = sc[r].rp;
+  if (rp == 2) {
+    const T beta = (T)sc[r].beta;
+    Spinor<T> pp;
+    load_spinor(pi, r, par, s, pp);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pp.v[k] = b.v[k] + beta * pp.v[k];
+    store_spinor(pi, r, par, s, pp);
+  } else if (rp == 1) {
+    store_spinor(pi, r, par, s, b);
+  }
 }
 
 template <typename SA, typename SB>
@@ -280,16 +290,17 @@ hipError_t launch_xpay_p(const Geom& g, Field<S> r, Field<S> p, const CgScalars*
   return hipGetLastError();
 }
 template <typename SX>
-hipError_t launch_fold(const Geom& g, Field<SX> xi, Field<double> x64, const CgScalars* sc, int n_rhs,
+hipError_t launch_fold(const Geom& g, Field<SX> xi, Field<double> x64, const CgScalars* sc, int n_rhs, int mode,
                        Shape sh, hipStream_t st) {
-  hipLaunchKernelGGL((fold_kernel<SX>), full_grid(g, sh, n_rhs), dim3(sh.sb, sh.nr), 0, st, g, xi, x64, sc, n_rhs);
+  hipLaunchKernelGGL((fold_kernel<SX>), full_grid(g, sh, n_rhs), dim3(sh.sb, sh.nr), 0, st, g, xi, x64, sc, n_rhs,
+                     mode);
   return hipGetLastError();
 }
 template <typename S>
-hipError_t launch_restart(const Geom& g, Field<double> r64, Field<S> ri, Field<S> pi, int set_p,
-                          const CgScalars* sc, int n_rhs, Shape sh, hipStream_t st) {
-  hipLaunchKernelGGL((restart_kernel<S>), full_grid(g, sh, n_rhs), dim3(sh.sb, sh.nr), 0, st, g, r64, ri, pi,
-                     set_p, sc, n_rhs);
+hipError_t launch_restart(const Geom& g, Field<double> r64, Field<S> ri, Field<S> pi, const CgScalars* sc,
+                          int n_rhs, Shape sh, hipStream_t st) {
+  hipLaunchKernelGGL((restart_kernel<S>), full_grid(g, sh, n_rhs), dim3(sh.sb, sh.nr), 0, st, g, r64, ri, pi, sc,
+                     n_rhs);
   return hipGetLastError();
 }
 template <typename SA, typename SB>
@@ -315,11 +326,11 @@ hipError_t launch_init_residual(const Geom& g, Field<double> b, Field<double> r6
 template hipError_t launch_xpay_p<double>(const Geom&, Field<double>, Field<double>, const CgScalars*, int, Shape, hipStream_t);
 template hipError_t launch_xpay_p<float>(const Geom&, Field<float>, Field<float>, const CgScalars*, int, Shape, hipStream_t);
 template hipError_t launch_xpay_p<_Float16>(const Geom&, Field<_Float16>, Field<_Float16>, const CgScalars*, int, Shape, hipStream_t);
-template hipError_t launch_fold<double>(const Geom&, Field<double>, Field<double>, const CgScalars*, int, Shape, hipStream_t);
-template hipError_t launch_fold<float>(const Geom&, Field<float>, Field<double>, const CgScalars*, int, Shape, hipStream_t);
-template hipError_t launch_restart<double>(const Geom&, Field<double>, Field<double>, Field<double>, int, const CgScalars*, int, Shape, hipStream_t);
-template hipError_t launch_restart<float>(const Geom&, Field<double>, Field<float>, Field<float>, int, const CgScalars*, int, Shape, hipStream_t);
-template hipError_t launch_restart<_Float16>(const Geom&, Field<double>, Field<_Float16>, Field<_Float16>, int, const CgScalars*, int, Shape, hipStream_t);
+template hipError_t launch_fold<double>(const Geom&, Field<double>, Field<double>, const CgScalars*, int, int, Shape, hipStream_t);
+template hipError_t launch_fold<float>(const Geom&, Field<float>, Field<double>, const CgScalars*, int, int, Shape, hipStream_t);
+template hipError_t launch_restart<double>(const Geom&, Field<double>, Field<double>, Field<double>, const CgScalars*, int, Shape, hipStream_t);
+template hipError_t launch_restart<float>(const Geom&, Field<double>, Field<float>, Field<float>, const CgScalars*, int, Shape, hipStream_t);
+template hipError_t launch_restart<_Float16>(const Geom&, Field<double>, Field<_Float16>, Field<_Float16>, const CgScalars*, int, Shape, hipStream_t);
 template hipError_t launch_convert<double, double>(const Geom&, Field<double>, Field<double>, int, int, Shape, hipStream_t);
 template hipError_t launch_convert<double, float>(const Geom&, Field<double>, Field<float>, int, int, Shape, hipStream_t);
 template hipError_t launch_convert<double, _Float16>(const Geom&, Field<double>, Field<_Float16>, int, int, Shape, hipStream_t);

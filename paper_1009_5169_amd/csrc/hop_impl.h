@@ -138,6 +138,7 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
   switch (fin) {
     case FIN_ALPHA:
       s.rp = 0;
+      s.fresh = 0;
       s.pap = sum;
       if (s.state == ST_ACTIVE && finite && sum > 0.0) {
         s.alpha = s.rho / sum;
@@ -148,21 +149,24 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
       break;
     case FIN_BETA:
       s.rp = 0;
+      s.fresh = 0;
       if (s.state == ST_ACTIVE) {
         s.beta = sum / s.rho;
         s.rho = sum;
         s.iters += 1;
-        if (!finite || sum <= tol2 * s.bnorm2) s.state = ST_CHECK;
-        if (sum < delta2 * s.rho_ru) s.upd = 1;
-      } else {
-        s.beta = 0.0;
+        if (!finite || sum <= tol2 * s.bnorm2)
+          s.state = ST_CHECK;
+        else if (sum < delta2 * s.rho_ru)
+          s.state = ST_WAIT;  // keeps beta for p = r + beta p after the update
       }
       break;
     case FIN_TRUE:
-      if (s.state != ST_DONE) {
-        // an RHS whose recursion claimed convergence (or broke down) keeps a
-        // search direction orthogonal to its residual: restart it with p = r
-        const int was_check = s.state == ST_CHECK;
+    case FIN_TRUE_FLAGGED:
+      if (in_update(s, fin == FIN_TRUE ? UPD_ALL : UPD_FLAGGED)) {
+        // continue from the true residual: a paused RHS finishes its step
+        // with p = r + beta p, one that claimed convergence (or broke down)
+        // restarts with p = r, one interrupted mid-recursion keeps p
+        const int was = s.state;
         s.rtrue2 = sum;
         s.n_true += 1;
         if (sum <= tol2 * s.bnorm2) {
@@ -171,16 +175,18 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
           s.state = ST_ACTIVE;
           s.rho = sum;
           s.rho_ru = sum;
-          s.rp = was_check;
+          s.rp = was == ST_CHECK ? 1 : (was == ST_WAIT ? 2 : 0);
+          s.fresh = 1;
         }
-        s.upd = 0;
       }
       break;
     case FIN_INIT:
       s.bnorm2 = sum;
       s.rho = s.rho_ru = s.rtrue2 = sum;
       s.alpha = s.beta = s.pap = 0.0;
-      s.iters = s.upd = s.n_true = s.rp = 0;
+      s.iters = s.n_true = 0;
+      s.rp = 1;
+      s.fresh = 1;
       s.state = sum > 0.0 ? ST_ACTIVE : ST_DONE;
       break;
   }

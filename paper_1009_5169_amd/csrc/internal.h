@@ -15,7 +15,11 @@ namespace mfq {
 // One record per right-hand side, in device memory.  Double-buffered copies
 // are not needed because every scalar update happens in a one-block
 // finishing kernel between the vector kernels.
-enum : int { ST_ACTIVE = 0, ST_CHECK = 1, ST_DONE = 2 };
+// ST_WAIT: the residual dropped by delta since the last true residual; the
+// RHS pauses until the reliable update (so that the update is never late),
+// keeping its search direction.  ST_CHECK: the recursion claims convergence
+// (or broke down); the update checks the truth and restarts p.
+enum : int { ST_ACTIVE = 0, ST_WAIT = 1, ST_CHECK = 2, ST_DONE = 3 };
 
 struct CgScalars {
   double rho;     // |r|^2 of the current (inner) residual
@@ -26,18 +30,28 @@ struct CgScalars {
   double pad;
   int state;  // ST_ACTIVE, ST_CHECK (needs a true-residual check), ST_DONE
   int iters;
-  int upd;    // reliable update requested (residual dropped by delta)
+  int pad1;
   int n_true; // true-residual evaluations
-  int rp;     // restart the search direction at the next restart (p = r)
-  int pad2;
+  int rp;     // at the next restart: 1 p = r, 2 p = r + beta p, 0 keep p
+  int fresh;  // the last true-residual evaluation covered this RHS: reload r
 };
+
+// Which RHS a reliable update covers: every unfinished one (UPD_ALL), or only
+// those that asked for it (UPD_FLAGGED: ST_WAIT or ST_CHECK), so that RHS and
+// lattices sharing one solve keep their own update schedule.
+enum : int { UPD_ALL = 0, UPD_FLAGGED = 1 };
+
+__host__ __device__ inline bool in_update(const CgScalars& s, int mode) {
+  return s.state != ST_DONE && (mode == UPD_ALL || s.state == ST_WAIT || s.state == ST_CHECK);
+}
 
 enum : int {
   FIN_STORE = 0,  // out[r] = sum
   FIN_ALPHA = 1,  // pap = sum; alpha = rho / pap
   FIN_BETA = 2,   // rho' = sum; beta = rho'/rho; convergence / update flags
-  FIN_TRUE = 3,   // true residual: done, or restart the recursion from it
+  FIN_TRUE = 3,   // true residual (every unfinished RHS): done, or restart the recursion from it
   FIN_INIT = 4,   // |b|^2: initial state
+  FIN_TRUE_FLAGGED = 5,  // as FIN_TRUE, for the RHS that asked for an update only
 };
 
 // Epilogues of the hopping kernel.
@@ -81,6 +95,7 @@ struct HopArgs {
   int anblk;
   int par;             // output parity 0 / 1, or 2 for both parities in one launch
   int n_rhs, dagger, skip_state;
+  int upd_mode;        // >= 0: run only the RHS in_update(sc[r], upd_mode); else use skip_state
   int xcd;             // set by the launcher from the Shape
   double coef;         // coefficient of the hopping term
 };
@@ -97,10 +112,10 @@ hipError_t launch_xpay_p(const Geom& g, Field<S> r, Field<S> p, const CgScalars*
                          Shape sh, hipStream_t st);
 template <typename SX>
 hipError_t launch_fold(const Geom& g, Field<SX> xi, Field<double> x64, const CgScalars* sc,
-                       int n_rhs, Shape sh, hipStream_t st);
+                       int n_rhs, int mode, Shape sh, hipStream_t st);
 template <typename S>
 hipError_t launch_restart(const Geom& g, Field<double> r64, Field<S> ri, Field<S> pi,
-                          int set_p, const CgScalars* sc, int n_rhs, Shape sh, hipStream_t st);
+                          const CgScalars* sc, int n_rhs, Shape sh, hipStream_t st);
 template <typename SA, typename SB>
 hipError_t launch_convert(const Geom& g, Field<SA> src, Field<SB> dst, int gamma5, int n_rhs,
                           Shape sh, hipStream_t st);

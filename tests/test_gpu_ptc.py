@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import native, ptc
+from oracle import native, ptc, solvers
 from oracle.dirac import WilsonDirac
 
 pytestmark = pytest.mark.gpu
@@ -130,37 +130,48 @@ def test_bad_network_falls_back_to_cg():
 
 
 def test_pairs_training_and_gain(tmp_path):
-    """Pairs from CG on training RHS, GPU training, and the gain of the trained
-    network: fewer FGMRES iterations than without the network on evaluation RHS
-    disjoint from the training ones."""
+    """Pairs from CG on b = A xi with known solutions xi, GPU training, and the
+    gain of the trained network: fewer FGMRES iterations than without the
+    network on evaluation RHS disjoint from the training ones."""
     dims, bc, kappa = (8, 8, 8, 8), "sf", 0.1375
     u = synth.random_links(dims, bc, 0.5, 1004)
     d = native.NativeWilson(dims, bc, kappa, u)
     lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
-    train_b = to_dev(synth.gaussian_spinors(dims, bc, 4, synth.PTC_TRAIN_SEED))
-    r, e = lat.precond_pairs(train_b, every=10, n_snap=4)
-    # the pairs are what CG made: e solves A e = r (to the oracle's FP64 residual)
+    xi = synth.gaussian_spinors(dims, bc, 4, synth.PTC_TRAIN_SEED)
+    r, e = lat.precond_pairs(to_dev(xi), every=5, n_snap=4)
     rh, eh = to_host(r), to_host(e)
-    res = np.linalg.norm(rh[:2] - d.DdagD(eh[:2])) / np.linalg.norm(rh[:2])
-    assert res < 1e-9, res
+    assert rh.shape == (16,) + xi.shape[1:]
+    # the first pair is (A xi, xi) / |A xi|, against the oracle operator
+    axi = d.DdagD(xi)
+    scale = np.linalg.norm(axi.reshape(4, -1), axis=1)[:, None, None, None, None, None, None]
+    assert rel(rh[:4], axi / scale) < 1e-12
+    assert rel(eh[:4], xi / scale) < 1e-12
+    # every pair satisfies A e = r (the CG iterates cancel) with |r| = 1
+    res = np.linalg.norm(rh - d.DdagD(eh)) / np.linalg.norm(rh)
+    assert res < 1e-12, res
+    np.testing.assert_allclose(np.linalg.norm(rh.reshape(16, -1), axis=1), 1.0, rtol=1e-12)
+    # the second pair is the oracle's CG iterate after 5 iterations on b = A xi
+    x5, _ = solvers.cg(d.DdagD, axi, 0.0, max_iter=5)
+    r5 = axi - d.DdagD(x5)
+    s5 = np.linalg.norm(r5.reshape(4, -1), axis=1)[:, None, None, None, None, None, None]
+    assert rel(rh[4:8], r5 / s5) < 1e-10
+    assert rel(eh[4:8], (xi - x5) / s5) < 1e-10
     lat.precond_init(seed=1)
-    hist = lat.precond_train(r, e, steps=150, lr=3e-3)
+    hist = lat.precond_train(r, e, steps=300, lr=3e-3)
     note(f"training loss {hist[0]:.4f} -> {hist[-1]:.4f}")
-    assert hist[-1] < 0.9 * hist[0]
+    assert hist[-1] < 0.5 * hist[0]
     path = str(tmp_path / "w.bin")
     lat.precond_save(path)
     w_trained = lat.precond_get_weights("master")
     b = synth.gaussian_spinors(dims, bc, 3, 2400)
     x_id, st_id, _ = lat.solve(to_dev(b), tol=1e-10, precond="identity", prec="fp64", max_iter=20000)
     x_pc, st_pc, rc = lat.solve(to_dev(b), tol=1e-10, precond="ptc", prec="fp64", max_iter=20000)
-    lat.precond_init(seed=1)
-    _, st_un, _ = lat.solve(to_dev(b), tol=1e-10, precond="ptc", prec="fp64", max_iter=20000)
     it_id = [s["iters"] for s in st_id]
     it_pc = [s["iters"] for s in st_pc]
-    note(f"FGMRES iterations: identity {it_id}, untrained PTC {[s['iters'] for s in st_un]}, trained PTC {it_pc}")
+    note(f"FGMRES(16) iterations: identity {it_id}, trained PTC {it_pc} (rc {rc})")
     assert rc == 0
     _solve_check(lat, d, b, x_pc, 1e-10)
-    assert sum(it_pc) < sum(it_id)
+    assert sum(it_pc) < 0.8 * sum(it_id)
     lat.precond_load(path)
     np.testing.assert_array_equal(lat.precond_get_weights("master"), w_trained)
     lat.close()
