@@ -14,6 +14,7 @@ half-dslash bandwidth on a lattice far larger than the 256 MB Infinity Cache.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +25,42 @@ sys.path.insert(0, ROOT)
 
 METRIC = "5-RHS D†D solve time to 1e-10 vs plain FP64 CG; dslash HBM GB/s, % peak"
 HBM_PEAK_GBS = 8000.0
+
+
+COUNTERS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                             "hop_kernel_counters_sf8x8x8x8_5rhs.txt")
+KERNEL_SOURCES = ("hop.hip", "hop_impl.h", "device.h", "internal.h")
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the sources of the hopping kernel: counter figures taken
+    with other sources do not describe the kernel that runs."""
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1009_5169_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(base, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec: str, n_rhs: int):
+    """HBM-side bytes per launch of the roofline kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
+    what the counter reads for a plain copy of known size), or None when the
+    summary is missing, is for another precision / RHS count, or was taken
+    with different kernel sources."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash() or kv.get("prec") != prec or int(kv.get("n_rhs", 0)) != n_rhs:
+        return None
+    copy_kib = float(kv["copy_bytes"]) / 1024.0
+    fetch = float(kv["fetch_kib_per_dispatch"]) * copy_kib / float(kv["copy_fetch_kib"])
+    write = float(kv["write_kib_per_dispatch"]) * copy_kib / float(kv["copy_write_kib"])
+    return int(round((fetch + write) * 1024))
 
 
 def hop_bytes_per_site_rhs(prec: str, n_rhs: int) -> float:
@@ -54,6 +91,8 @@ def main():
     ap.add_argument("--bw-dims", default="32,32,32,64")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the batch, FP16 and learned-preconditioner measurements")
+    ap.add_argument("--profile-big", action="store_true",
+                    help="with --profile-kernels: also the bandwidth lattice, 1 and 5 RHS")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the roofline kernel (solve shape) and a 1 GiB copy, for counter runs")
     args = ap.parse_args()
@@ -71,7 +110,7 @@ def main():
     dev = "cuda:0"
     p = synth.CONFIG_1
     if args.profile_kernels:
-        profile_kernels(args, synth, mfq, torch, dev)
+        profile_kernels(args, synth, mfq, torch, dev, np)
         return
     u = p.links()
     phi_h = p.rhs()
@@ -103,7 +142,7 @@ def main():
     per_launch = hop_bytes_per_site_rhs(args.prec, n) * vd * n
     achieved = per_launch / (hop_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.prec, n),
                 "kernel": f"hop_kernel<EPI_D,{args.prec}> (both parities)", "launch_us": round(hop_ms * 1e3, 3),
                 "shape": list(lat.hop_shape(args.prec, n)),
                 "algorithmic_bytes_per_launch": int(per_launch)}
@@ -146,14 +185,7 @@ def main():
     if not args.no_bandwidth:
         dims = tuple(int(v) for v in args.bw_dims.split(","))
         print(f"[bench] bandwidth lattice {dims}", file=sys.stderr, flush=True)
-        # random SU(3) links on a 16^3 x 8 block, tiled over the lattice: the
-        # values do not matter for bandwidth and numpy's 3x3 eigh is slow
-        blk = (min(16, dims[0]), min(16, dims[1]), min(16, dims[2]), min(8, dims[3]))
-        ub = synth.random_links(blk, "periodic", 0.3, 7)
-        reps = (1, dims[3] // blk[3], dims[2] // blk[2], dims[1] // blk[1], dims[0] // blk[0], 1, 1)
-        ub = np.ascontiguousarray(np.tile(ub, reps))
-        big = mfq.Lattice(dims, "periodic", 0.12, torch.from_numpy(ub).to(dev))
-        del ub
+        big = bandwidth_lattice(dims, synth, mfq, torch, dev, np)
         bw = {}
         vdb = dims[0] * dims[1] * dims[2] * dims[3]
         for prec in ("fp64", "fp32", "fp16"):
@@ -309,21 +341,44 @@ def bench_batch(synth, mfq, torch, dev, np):
     return res
 
 
-def profile_kernels(args, synth, mfq, torch, dev):
-    """Counter run: the fused half-dslash of the inner CG on the bench lattice
-    (its tuned launch shape, 50 launches) and a plain 1 GiB device copy, whose
-    FETCH_SIZE / WRITE_SIZE calibrate the counters against known bytes."""
+def bandwidth_lattice(dims, synth, mfq, torch, dev, np):
+    """Periodic lattice for the bandwidth runs: random SU(3) links on a 16^3 x 8
+    block, tiled over the lattice (the values do not matter for bandwidth and
+    numpy's 3x3 eigh is slow)."""
+    blk = (min(16, dims[0]), min(16, dims[1]), min(16, dims[2]), min(8, dims[3]))
+    ub = synth.random_links(blk, "periodic", 0.3, 7)
+    reps = (1, dims[3] // blk[3], dims[2] // blk[2], dims[1] // blk[1], dims[0] // blk[0], 1, 1)
+    ub = np.ascontiguousarray(np.tile(ub, reps))
+    return mfq.Lattice(dims, "periodic", 0.12, torch.from_numpy(ub).to(dev))
+
+
+def profile_kernels(args, synth, mfq, torch, dev, np):
+    """Counter run: the hopping kernel of the inner CG on the bench lattice
+    (its tuned launch shape, 50 timed launches after the tuner's), a plain
+    1 GiB device copy, whose FETCH_SIZE / WRITE_SIZE calibrate the counters
+    against known bytes, and with --profile-big the same kernel on the
+    bandwidth lattice for 1 and 5 RHS."""
     p = synth.CONFIG_1
+    out = {"profile_kernels": True}
     lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
-    ms = lat.time_hop(args.prec, p.n_rhs, iters=50)
-    shape = lat.hop_shape(args.prec, p.n_rhs)
+    out["hop_ms"] = lat.time_hop(args.prec, p.n_rhs, iters=50)
+    out["shape"] = lat.hop_shape(args.prec, p.n_rhs)
+    lat.close()
     src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_kernels": True, "hop_ms": ms, "shape": shape, "copy_bytes": src.numel() * 8}))
-    lat.close()
+    out["copy_bytes"] = src.numel() * 8
+    del src, dst
+    if args.profile_big:
+        dims = tuple(int(v) for v in args.bw_dims.split(","))
+        big = bandwidth_lattice(dims, synth, mfq, torch, dev, np)
+        for nr in (1, 5):
+            out[f"big_n{nr}_ms"] = big.time_hop(args.prec, nr, iters=20)
+            out[f"big_n{nr}_shape"] = big.hop_shape(args.prec, nr)
+        big.close()
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -85,7 +85,7 @@ int check_lattice(const mfq_lattice* lat) {
 
 int partials_ready(mfq_handle* h, int n_rhs) {
   Workspace& w = h->ws;
-  const int nblk = (2 * h->g.vh + 63) / 64;
+  const int nblk = 2 * ((h->g.vh + 63) / 64);  // >= any launch's workgroups along x
   if (w.cap_part < n_rhs || w.nblk_max < nblk) {
     HIPCHK(ensure(w.part, sizeof(double) * 4 * (size_t)n_rhs * nblk));
     HIPCHK(ensure(w.sc, sizeof(CgScalars) * n_rhs));
@@ -307,7 +307,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   // Both parities per launch: the D half reads only p, the D^+ half only t.
   // On small lattices alpha is reduced inside the update kernel (one launch
   // fewer); larger ones use the finishing kernel.
-  const int nb2 = (2 * g.vh + sh.sb - 1) / sh.sb;
+  const int nb2 = hop_grid_x(g, sh, 2);
   const bool fuse_alpha = nb2 <= 256;
   auto iteration = [&](hipStream_t st) -> int {
     // t = D p, partial |t|^2 = p^+ D^+ D p

@@ -57,19 +57,25 @@ __device__ __forceinline__ double cg_alpha(const HopArgs<S, SX>& a, int r) {
   return s_alpha[threadIdx.y];
 }
 
+// With both parities in one launch (par == 2) consecutive tiles alternate
+// parity over the same half-index range: the two tiles share the links of
+// their rows (the forward link of one parity is the backward link of the
+// other) and each other's spinors, so they meet in the same XCD's L2.
 template <int EPI, typename S, typename SX>
 __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
-  int s = tile_index(a.xcd) * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y * blockDim.y + threadIdx.y;
+  const int tile = tile_index(a.xcd);
   int par = a.par;
-  const int nsites = par == 2 ? 2 * a.g.vh : a.g.vh;
+  int s;
+  if (par == 2) {
+    par = tile & 1;
+    s = (tile >> 1) * blockDim.x + threadIdx.x;
+  } else {
+    s = tile * blockDim.x + threadIdx.x;
+  }
+  const int r = blockIdx.y * blockDim.y + threadIdx.y;
   double alpha = 0.0;
   if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r);
-  bool active = s < nsites && r < a.n_rhs;
-  if (par == 2) {
-    par = s >= a.g.vh ? 1 : 0;
-    s -= par * a.g.vh;
-  }
+  bool active = s < a.g.vh && r < a.n_rhs;
   if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
   const double red = active ? hop_site<EPI>(a, par, s, r, alpha) : 0.0;
   if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
@@ -91,13 +97,15 @@ Shape default_shape(int n_rhs) {
   return sh;
 }
 
-int blocks_for(const Geom&, Shape sh, int n_sites) { return (n_sites + sh.sb - 1) / sh.sb; }
+int hop_grid_x(const Geom& g, Shape sh, int par) {
+  const int per_parity = (g.vh + sh.sb - 1) / sh.sb;
+  return par == 2 ? 2 * per_parity : per_parity;
+}
 
 template <typename S, typename SX>
 hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st) {
   dim3 block(sh.sb, sh.nr);
-  const int nsites = a.par == 2 ? 2 * a.g.vh : a.g.vh;
-  dim3 grid((nsites + sh.sb - 1) / sh.sb, (a.n_rhs + sh.nr - 1) / sh.nr);
+  dim3 grid(hop_grid_x(a.g, sh, a.par), (a.n_rhs + sh.nr - 1) / sh.nr);
   HopArgs<S, SX> b = a;
   b.xcd = sh.xcd;
   switch (epi) {

@@ -54,79 +54,69 @@ __device__ __forceinline__ void block_partial(double v, double* part, int n_rhs,
 
 // One direction mu of the hopping term: forward hop from n+mu through U_mu(n),
 // backward hop from n-mu through U_mu(n-mu)^+.  sgf / sgb are the projector
-// signs (-1 / +1 for H, +1 / -1 for H^+).
+// signs (-1 / +1 for H, +1 / -1 for H^+).  The time boundary is folded into a
+// factor (0 across a Schroedinger-functional boundary, -1 across an
+// antiperiodic wrap) on a neighbour index that always stays inside the
+// lattice, so the loads of every direction are unconditional and can be
+// issued together.
 template <int MU, typename S, typename SX, typename T>
 __device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, int par, const Coords& c, int s, int r,
                                         T sgf, T sgb, Spinor<T>& acc) {
   const Geom& g = a.g;
   const int po = 1 - par;
-  {  // forward
-    int x = c.x, y = c.y, z = c.z, t = c.t;
-    T sgn = (T)1;
-    bool ok = true;
-    if constexpr (MU == 0) {
-      t = c.t + 1;
-      if (t == g.td) {
-        if (g.bc == BC_SF) ok = false;
-        t = 0;
-        if (g.bc == BC_ANTIPERIODIC) sgn = (T)-1;
-      }
-    } else if constexpr (MU == 1) {
-      x = (c.x + 1 == g.lx) ? 0 : c.x + 1;
-    } else if constexpr (MU == 2) {
-      y = (c.y + 1 == g.ly) ? 0 : c.y + 1;
-    } else {
-      z = (c.z + 1 == g.lz) ? 0 : c.z + 1;
+  int xf = c.x, yf = c.y, zf = c.z, tf = c.t;
+  int xb = c.x, yb = c.y, zb = c.z, tb = c.t;
+  T wf = (T)1, wb = (T)1;
+  if constexpr (MU == 0) {
+    const T wrap = g.bc == BC_SF ? (T)0 : (g.bc == BC_ANTIPERIODIC ? (T)-1 : (T)1);
+    tf = c.t + 1;
+    if (tf == g.td) {
+      tf = 0;
+      wf = wrap;
     }
-    if (ok) {
-      Spinor<T> nb;
-      load_spinor(a.in, r, po, half_index(g, x, y, z, t), nb);
-      cpx<T> u[9];
-      load_link(a.links, par, MU, s, u);
-      cpx<T> h0[3], h1[3];
+    tb = c.t - 1;
+    if (tb < 0) {
+      tb = g.td - 1;
+      wb = wrap;
+    }
+  } else if constexpr (MU == 1) {
+    xf = (c.x + 1 == g.lx) ? 0 : c.x + 1;
+    xb = (c.x == 0) ? g.lx - 1 : c.x - 1;
+  } else if constexpr (MU == 2) {
+    yf = (c.y + 1 == g.ly) ? 0 : c.y + 1;
+    yb = (c.y == 0) ? g.ly - 1 : c.y - 1;
+  } else {
+    zf = (c.z + 1 == g.lz) ? 0 : c.z + 1;
+    zb = (c.z == 0) ? g.lz - 1 : c.z - 1;
+  }
+  const int sf = half_index(g, xf, yf, zf, tf);
+  const int sbk = half_index(g, xb, yb, zb, tb);
+  Spinor<T> nf, nb;
+  cpx<T> uf[9], ub[9];
+  load_spinor(a.in, r, po, sf, nf);
+  load_link(a.links, par, MU, s, uf);
+  load_spinor(a.in, r, po, sbk, nb);
+  load_link(a.links, po, MU, sbk, ub);
+  {  // forward
+    cpx<T> h0[3], h1[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) project<MU>(nb, sgf, k, h0[k], h1[k]);
+    for (int k = 0; k < 3; ++k) project<MU>(nf, sgf, k, h0[k], h1[k]);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        cpx<T> g0 = cmul(u[3 * i], h0[0]) + cmul(u[3 * i + 1], h0[1]) + cmul(u[3 * i + 2], h0[2]);
-        cpx<T> g1 = cmul(u[3 * i], h1[0]) + cmul(u[3 * i + 1], h1[1]) + cmul(u[3 * i + 2], h1[2]);
-        reconstruct<MU>(acc, sgf, i, sgn * g0, sgn * g1);
-      }
+    for (int i = 0; i < 3; ++i) {
+      cpx<T> g0 = cmul(uf[3 * i], h0[0]) + cmul(uf[3 * i + 1], h0[1]) + cmul(uf[3 * i + 2], h0[2]);
+      cpx<T> g1 = cmul(uf[3 * i], h1[0]) + cmul(uf[3 * i + 1], h1[1]) + cmul(uf[3 * i + 2], h1[2]);
+      reconstruct<MU>(acc, sgf, i, wf * g0, wf * g1);
     }
   }
-  {  // backward
-    int x = c.x, y = c.y, z = c.z, t = c.t;
-    T sgn = (T)1;
-    bool ok = true;
-    if constexpr (MU == 0) {
-      t = c.t - 1;
-      if (t < 0) {
-        if (g.bc == BC_SF) ok = false;
-        t = g.td - 1;
-        if (g.bc == BC_ANTIPERIODIC) sgn = (T)-1;
-      }
-    } else if constexpr (MU == 1) {
-      x = (c.x == 0) ? g.lx - 1 : c.x - 1;
-    } else if constexpr (MU == 2) {
-      y = (c.y == 0) ? g.ly - 1 : c.y - 1;
-    } else {
-      z = (c.z == 0) ? g.lz - 1 : c.z - 1;
-    }
-    if (ok) {
-      const int sb = half_index(g, x, y, z, t);
-      Spinor<T> nb;
-      load_spinor(a.in, r, po, sb, nb);
-      cpx<T> u[9];
-      load_link(a.links, po, MU, sb, u);
-      cpx<T> h0[3], h1[3];
+  {  // backward: (U^+)_{ik} = conj(U_{ki})
+    cpx<T> h0[3], h1[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) project<MU>(nb, sgb, k, h0[k], h1[k]);
+    for (int k = 0; k < 3; ++k) project<MU>(nb, sgb, k, h0[k], h1[k]);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {  // (U^+)_{ik} = conj(U_{ki})
-        cpx<T> g0 = cjmul(u[i], h0[0]) + cjmul(u[3 + i], h0[1]) + cjmul(u[6 + i], h0[2]);
-        cpx<T> g1 = cjmul(u[i], h1[0]) + cjmul(u[3 + i], h1[1]) + cjmul(u[6 + i], h1[2]);
-        reconstruct<MU>(acc, sgb, i, sgn * g0, sgn * g1);
-      }
+    for (int i = 0; i < 3; ++i) {
+      cpx<T> g0 = cjmul(ub[i], h0[0]) + cjmul(ub[3 + i], h0[1]) + cjmul(ub[6 + i], h0[2]);
+      cpx<T> g1 = cjmul(ub[i], h1[0]) + cjmul(ub[3 + i], h1[1]) + cjmul(ub[6 + i], h1[2]);
+      reconstruct<MU>(acc, sgb, i, wb * g0, wb * g1);
     }
   }
 }

@@ -75,7 +75,8 @@ struct Shape {
 };
 
 Shape default_shape(int n_rhs);
-int blocks_for(const Geom& g, Shape sh, int n_sites);
+// Workgroups along x of a hopping launch (par 0 / 1, or 2 for both parities).
+int hop_grid_x(const Geom& g, Shape sh, int par);
 
 // The hopping kernel, all precisions and epilogues.
 template <typename S, typename SX>
