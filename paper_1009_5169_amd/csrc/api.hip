@@ -85,7 +85,7 @@ int check_lattice(const mfq_lattice* lat) {
 
 int partials_ready(mfq_handle* h, int n_rhs) {
   Workspace& w = h->ws;
-  const int nblk = 2 * ((h->g.vh + 63) / 64);  // >= any launch's workgroups along x
+  const int nblk = max_hop_blocks(h->g);  // >= any launch's workgroups along x
   if (w.cap_part < n_rhs || w.nblk_max < nblk) {
     HIPCHK(ensure(w.part, sizeof(double) * 4 * (size_t)n_rhs * nblk));
     HIPCHK(ensure(w.sc, sizeof(CgScalars) * n_rhs));
@@ -197,14 +197,15 @@ bool tune_cache_lookup(mfq_handle* h, int n, int prec, Shape* out) {
   char line[256];
   bool found = false;
   while (fgets(line, sizeof(line), f)) {
-    int sb, nr, xcd;
+    int sb, nr, xcd, tc;
     const char* bar = strchr(line, '|');
     if (!bar || std::string(line, bar - line) != key) continue;
-    if (sscanf(bar + 1, "%d %d %d", &sb, &nr, &xcd) == 3 && sb >= 64 && sb % 64 == 0 && nr >= 1 &&
-        sb * nr <= 512) {
+    if (sscanf(bar + 1, "%d %d %d %d", &sb, &nr, &xcd, &tc) == 4 && sb >= 64 && sb % 64 == 0 && nr >= 1 &&
+        sb * nr <= 512 && (tc == 0 || tc == 2 || tc == 4 || tc == 8 || tc == 16)) {
       out->sb = sb;
       out->nr = nr;
-      out->xcd = xcd;
+      out->xcd = xcd ? 1 : 0;
+      out->tc = tc;
       found = true;
     }
   }
@@ -231,18 +232,21 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
     for (int k = 0; k < 4; ++k) {
       const int nr = nrs[k];
       if (nr > n || sb * nr > 512 || (k > 0 && nr == nrs[k - 1])) continue;
-      for (int xcd = 0; xcd < 2; ++xcd) {
-        Shape sh{sb, nr, xcd};
-        for (int i = 0; i < 2; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
-        HIPCHK(hipEventRecord(h->ev0, st));
-        for (int i = 0; i < 10; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
-        HIPCHK(hipEventRecord(h->ev1, st));
-        HIPCHK(hipEventSynchronize(h->ev1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-        if (ms < best * 0.97f) {  // prefer earlier (simpler) shapes on near ties
-          best = ms;
-          best_sh = sh;
+      for (int tc = 0; tc <= 4; tc += 4) {  // the time sweep measured slower so far: one candidate
+        if (tc >= 2 * h->g.td) continue;  // one chunk already covers the time extent
+        for (int xcd = 0; xcd < 2; ++xcd) {
+          Shape sh{sb, nr, xcd, tc};
+          for (int i = 0; i < 2; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+          HIPCHK(hipEventRecord(h->ev0, st));
+          for (int i = 0; i < 10; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+          HIPCHK(hipEventRecord(h->ev1, st));
+          HIPCHK(hipEventSynchronize(h->ev1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+          if (ms < best * 0.97f) {  // prefer earlier (simpler) shapes on near ties
+            best = ms;
+            best_sh = sh;
+          }
         }
       }
     }
@@ -250,7 +254,8 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
   h->tuned.push_back({n, prec, best_sh, best * 100.f});
   if (const char* path = getenv("MFQ_AUTOTUNE_CACHE")) {
     if (FILE* f = fopen(path, "a")) {
-      fprintf(f, "%s|%d %d %d\n", tune_key(h, n, prec).c_str(), best_sh.sb, best_sh.nr, best_sh.xcd);
+      fprintf(f, "%s|%d %d %d %d\n", tune_key(h, n, prec).c_str(), best_sh.sb, best_sh.nr, best_sh.xcd,
+              best_sh.tc);
       fclose(f);
     }
   }
@@ -376,7 +381,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
                                   (uintptr_t)in.r.data, (uintptr_t)in.p.data, (uintptr_t)in.t.data,
                                   (uintptr_t)in.x.data, (uintptr_t)in.L.data, (uintptr_t)w.part.ptr,
                                   (uintptr_t)sc, bits(tol2), bits(delta2), (uintptr_t)sh.sb,
-                                  (uintptr_t)sh.nr, (uintptr_t)sh.xcd};
+                                  (uintptr_t)sh.nr, (uintptr_t)sh.xcd, (uintptr_t)sh.tc};
     GraphEntry* hit = nullptr;
     for (auto& e : h->graphs)
       if (e.key == key) hit = &e;
@@ -770,19 +775,15 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
   }
 }
 
-int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape3) {
-  if (!h || !shape3) return fail(MFQ_ERR_ARG, "NULL argument");
+int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape4) {
+  if (!h || !shape4) return fail(MFQ_ERR_ARG, "NULL argument");
+  Shape sh = default_shape(n_rhs);
   for (auto& e : h->tuned)
-    if (e.n == n_rhs && e.prec == (prec == 0 ? 8 : prec == 1 ? 4 : 2)) {
-      shape3[0] = e.sh.sb;
-      shape3[1] = e.sh.nr;
-      shape3[2] = e.sh.xcd;
-      return MFQ_OK;
-    }
-  const Shape sh = default_shape(n_rhs);
-  shape3[0] = sh.sb;
-  shape3[1] = sh.nr;
-  shape3[2] = sh.xcd;
+    if (e.n == n_rhs && e.prec == (prec == 0 ? 8 : prec == 1 ? 4 : 2)) sh = e.sh;
+  shape4[0] = sh.sb;
+  shape4[1] = sh.nr;
+  shape4[2] = sh.xcd;
+  shape4[3] = sh.tc;
   return MFQ_OK;
 }
 

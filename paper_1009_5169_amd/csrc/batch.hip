@@ -31,7 +31,7 @@ struct BatchLat {
   Field<double> x64, r64, b64;
   CgScalars* sc;
   double* part[4];
-  int nblk_half, nblk_full, nr, sb, n_rhs;
+  int nblk_both, nblk_full, nr, sb, n_rhs;  // tiles per RHS group: both-parity launches, vector kernels
 };
 
 struct Tile {
@@ -68,14 +68,19 @@ enum : int { BV_XPAY = 0, BV_FOLD = 1, BV_RESTART = 2, BV_INIT = 3 };
 
 constexpr int kBatchThreads = 512;
 
+// Both parities per launch: tile 2k and 2k+1 of a lattice cover the same
+// half-index range at parity 0 and 1 (the D half reads only p, the D^+ half
+// only t, so the parities are independent).
 template <int MODE, typename S, typename SX>
 __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat<S, SX>* lats, const Tile* tiles,
-                                                                  int n_tiles, int par, int slot, int mode) {
+                                                                  const int* n_tiles_dev, int slot, int mode) {
+  const int n_tiles = *n_tiles_dev;
   for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
     const Tile tl = tiles[it];
     const BatchLat<S, SX>& L = lats[tl.lat];
     const int row = threadIdx.x / L.sb;
-    const int s = tl.tile * L.sb + (threadIdx.x - row * L.sb);
+    const int par = tl.tile & 1;
+    const int s = (tl.tile >> 1) * L.sb + (threadIdx.x - row * L.sb);
     const int r = tl.rgrp * L.nr + row;
     double red = 0.0;
     if constexpr (MODE == BM_D || MODE == BM_CG) {
@@ -87,13 +92,14 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat
       if (s < a.g.vh && r < a.n_rhs && in_update(a.sc[r], mode))
         red = hop_site<MODE == BM_D64 ? EPI_D : EPI_RES>(a, par, s, r, 0.0);
     }
-    if (slot >= 0) tile_partial(red, L.part[slot + par], L.n_rhs, tl.rgrp * L.nr, L.sb, tl.tile, L.nblk_half);
+    if (slot >= 0) tile_partial(red, L.part[slot], L.n_rhs, tl.rgrp * L.nr, L.sb, tl.tile, L.nblk_both);
   }
 }
 
 template <int MODE, typename S, typename SX>
 __global__ __launch_bounds__(kBatchThreads) void batch_vec_kernel(const BatchLat<S, SX>* lats, const Tile* tiles,
-                                                                  int n_tiles, int mode) {
+                                                                  const int* n_tiles_dev, int mode) {
+  const int n_tiles = *n_tiles_dev;
   using T = typename Compute<S>::T;
   using TX = typename Compute<SX>::T;
   for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
@@ -189,6 +195,14 @@ struct mfq_batch {
   int prec = 0, total = 0;
   DevBuf lats, tiles_h, tiles_f, items[4], sc;
   int n_tiles_h = 0, n_tiles_f = 0, n_items[4] = {0, 0, 0, 0};
+  // Tiles of each lattice, and the lattices still in the lists: lattices whose
+  // RHS are all done are dropped from the launch lists between polls (the
+  // kernels read the list lengths from device memory, so captured graphs stay
+  // valid).
+  std::vector<std::vector<Tile>> lat_th, lat_tf;
+  std::vector<char> in_list;
+  std::vector<Tile> host_th, host_tf;
+  DevBuf counts;  // int[2]: current lengths of the two lists
   int grid = 512;
   CgScalars* host_sc = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -200,9 +214,11 @@ struct mfq_batch {
 
 namespace {
 
-int next_pow2_le8(int n) {
+// RHS rows per tile: the largest power of two (<= 8) dividing n, so that no
+// row of a 512-thread tile is idle (a tile is 512 / rows sites x rows RHS).
+int rows_per_tile(int n) {
   int p = 1;
-  while (p < n && p < 8) p *= 2;
+  while (p < 8 && n % (2 * p) == 0) p *= 2;
   return p;
 }
 
@@ -277,6 +293,8 @@ int batch_setup(mfq_batch* B) {
   std::vector<Tile> th, tf;
   std::vector<FinItem> items[4];
   CgScalars* sc = (CgScalars*)B->sc.ptr;
+  B->lat_th.assign(n_lat, {});
+  B->lat_tf.assign(n_lat, {});
   for (int i = 0; i < n_lat; ++i) {
     mfq_handle* h = B->hs[i];
     const int n = B->n_rhs[i];
@@ -289,9 +307,9 @@ int batch_setup(mfq_batch* B) {
     BatchLat<S, SX>& L = lats[i];
     memset((void*)&L, 0, sizeof(L));
     L.n_rhs = n;
-    L.nr = next_pow2_le8(n);
+    L.nr = rows_per_tile(n);
     L.sb = kBatchThreads / L.nr;
-    L.nblk_half = (g.vh + L.sb - 1) / L.sb;
+    L.nblk_both = 2 * ((g.vh + L.sb - 1) / L.sb);
     L.nblk_full = (2 * g.vh + L.sb - 1) / L.sb;
     L.sc = sc + B->off[i];
     for (int q = 0; q < 4; ++q) L.part[q] = part_slot(h, q);
@@ -326,15 +344,19 @@ int batch_setup(mfq_batch* B) {
     L.res.r64 = L.r64;
     L.res.dagger = 1;
     const int ng = (n + L.nr - 1) / L.nr;
+    B->lat_th[i].clear();
+    B->lat_tf[i].clear();
     for (int rg = 0; rg < ng; ++rg) {
-      for (int t = 0; t < L.nblk_half; ++t) th.push_back({i, t, rg});
-      for (int t = 0; t < L.nblk_full; ++t) tf.push_back({i, t, rg});
+      for (int t = 0; t < L.nblk_both; ++t) B->lat_th[i].push_back({i, t, rg});
+      for (int t = 0; t < L.nblk_full; ++t) B->lat_tf[i].push_back({i, t, rg});
     }
+    th.insert(th.end(), B->lat_th[i].begin(), B->lat_th[i].end());
+    tf.insert(tf.end(), B->lat_tf[i].begin(), B->lat_tf[i].end());
     for (int r = 0; r < n; ++r) {
       const size_t ro = (size_t)r;
-      items[FI_ALPHA].push_back({L.sc + r, L.part[0] + ro * L.nblk_half, L.part[1] + ro * L.nblk_half, L.nblk_half});
-      items[FI_BETA].push_back({L.sc + r, L.part[2] + ro * L.nblk_half, L.part[3] + ro * L.nblk_half, L.nblk_half});
-      items[FI_TRUE].push_back({L.sc + r, L.part[0] + ro * L.nblk_half, L.part[1] + ro * L.nblk_half, L.nblk_half});
+      items[FI_ALPHA].push_back({L.sc + r, L.part[0] + ro * L.nblk_both, nullptr, L.nblk_both});
+      items[FI_BETA].push_back({L.sc + r, L.part[2] + ro * L.nblk_both, nullptr, L.nblk_both});
+      items[FI_TRUE].push_back({L.sc + r, L.part[0] + ro * L.nblk_both, nullptr, L.nblk_both});
       items[FI_INIT].push_back({L.sc + r, L.part[0] + ro * L.nblk_full, nullptr, L.nblk_full});
     }
   }
@@ -346,6 +368,10 @@ int batch_setup(mfq_batch* B) {
   HIPCHK(hipMemcpy(B->tiles_f.ptr, tf.data(), sizeof(Tile) * tf.size(), hipMemcpyHostToDevice));
   B->n_tiles_h = (int)th.size();
   B->n_tiles_f = (int)tf.size();
+  HIPCHK(ensure(B->counts, 2 * sizeof(int)));
+  const int cnt[2] = {B->n_tiles_h, B->n_tiles_f};
+  HIPCHK(hipMemcpy(B->counts.ptr, cnt, sizeof(cnt), hipMemcpyHostToDevice));
+  B->in_list.assign(n_lat, 1);
   for (int k = 0; k < 4; ++k) {
     HIPCHK(ensure(B->items[k], sizeof(FinItem) * items[k].size()));
     HIPCHK(hipMemcpy(B->items[k].ptr, items[k].data(), sizeof(FinItem) * items[k].size(), hipMemcpyHostToDevice));
@@ -356,15 +382,16 @@ int batch_setup(mfq_batch* B) {
 }
 
 template <typename S, typename SX>
-hipError_t bhop(mfq_batch* B, int mode, int par, int slot, hipStream_t st, int upd_mode = UPD_ALL) {
+hipError_t bhop(mfq_batch* B, int mode, int slot, hipStream_t st, int upd_mode = UPD_ALL) {
   const BatchLat<S, SX>* L = (const BatchLat<S, SX>*)B->lats.ptr;
   const Tile* t = (const Tile*)B->tiles_h.ptr;
   const int grid = B->grid < B->n_tiles_h ? B->grid : B->n_tiles_h;
+  const int* nt = (const int*)B->counts.ptr;
   switch (mode) {
-    case BM_D: hipLaunchKernelGGL((batch_hop_kernel<BM_D, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
-    case BM_CG: hipLaunchKernelGGL((batch_hop_kernel<BM_CG, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
-    case BM_D64: hipLaunchKernelGGL((batch_hop_kernel<BM_D64, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
-    default: hipLaunchKernelGGL((batch_hop_kernel<BM_RES, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_h, par, slot, upd_mode); break;
+    case BM_D: hipLaunchKernelGGL((batch_hop_kernel<BM_D, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot, upd_mode); break;
+    case BM_CG: hipLaunchKernelGGL((batch_hop_kernel<BM_CG, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot, upd_mode); break;
+    case BM_D64: hipLaunchKernelGGL((batch_hop_kernel<BM_D64, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot, upd_mode); break;
+    default: hipLaunchKernelGGL((batch_hop_kernel<BM_RES, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot, upd_mode); break;
   }
   return hipGetLastError();
 }
@@ -374,11 +401,12 @@ hipError_t bvec(mfq_batch* B, int mode, int arg, hipStream_t st) {
   const BatchLat<S, SX>* L = (const BatchLat<S, SX>*)B->lats.ptr;
   const Tile* t = (const Tile*)B->tiles_f.ptr;
   const int grid = B->grid < B->n_tiles_f ? B->grid : B->n_tiles_f;
+  const int* nt = (const int*)B->counts.ptr + 1;
   switch (mode) {
-    case BV_XPAY: hipLaunchKernelGGL((batch_vec_kernel<BV_XPAY, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
-    case BV_FOLD: hipLaunchKernelGGL((batch_vec_kernel<BV_FOLD, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
-    case BV_RESTART: hipLaunchKernelGGL((batch_vec_kernel<BV_RESTART, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
-    default: hipLaunchKernelGGL((batch_vec_kernel<BV_INIT, S, SX>), grid, kBatchThreads, 0, st, L, t, B->n_tiles_f, arg); break;
+    case BV_XPAY: hipLaunchKernelGGL((batch_vec_kernel<BV_XPAY, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, arg); break;
+    case BV_FOLD: hipLaunchKernelGGL((batch_vec_kernel<BV_FOLD, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, arg); break;
+    case BV_RESTART: hipLaunchKernelGGL((batch_vec_kernel<BV_RESTART, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, arg); break;
+    default: hipLaunchKernelGGL((batch_vec_kernel<BV_INIT, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, arg); break;
   }
   return hipGetLastError();
 }
@@ -399,9 +427,9 @@ int batch_tune(mfq_batch* B, hipStream_t st) {
   const int cands[4] = {256, 512, 1024, 2048};
   for (int c = 0; c < 4; ++c) {
     B->grid = cands[c];
-    for (int i = 0; i < 2; ++i) HIPCHK(bhop<S, SX>(B, BM_D, 0, -1, st));
+    for (int i = 0; i < 2; ++i) HIPCHK(bhop<S, SX>(B, BM_D, -1, st));
     HIPCHK(hipEventRecord(B->ev0, st));
-    for (int i = 0; i < 5; ++i) HIPCHK(bhop<S, SX>(B, BM_D, i & 1, -1, st));
+    for (int i = 0; i < 5; ++i) HIPCHK(bhop<S, SX>(B, BM_D, -1, st));
     HIPCHK(hipEventRecord(B->ev1, st));
     HIPCHK(hipEventSynchronize(B->ev1));
     float ms = 0.f;
@@ -423,6 +451,39 @@ void batch_drop_graphs(mfq_batch* B) {
   B->graphs.clear();
 }
 
+// Drop the lattices whose RHS are all done (host_sc holds the last poll) from
+// the launch lists, or restore all (every = true).  The copies run on the
+// solve stream before the next launches; the host lists stay alive in the
+// batch until the next rebuild, which happens only after a stream sync.
+int batch_relist(mfq_batch* B, bool every, hipStream_t st) {
+  const int n_lat = (int)B->hs.size();
+  bool changed = false;
+  for (int i = 0; i < n_lat; ++i) {
+    bool live = every;
+    for (int r = 0; r < B->n_rhs[i] && !live; ++r) live = B->host_sc[B->off[i] + r].state != ST_DONE;
+    if ((char)live != B->in_list[i]) {
+      B->in_list[i] = live;
+      changed = true;
+    }
+  }
+  if (!changed) return MFQ_OK;
+  B->host_th.clear();
+  B->host_tf.clear();
+  for (int i = 0; i < n_lat; ++i)
+    if (B->in_list[i]) {
+      B->host_th.insert(B->host_th.end(), B->lat_th[i].begin(), B->lat_th[i].end());
+      B->host_tf.insert(B->host_tf.end(), B->lat_tf[i].begin(), B->lat_tf[i].end());
+    }
+  static thread_local int cnt[2];
+  cnt[0] = (int)B->host_th.size();
+  cnt[1] = (int)B->host_tf.size();
+  if (cnt[0]) HIPCHK(hipMemcpyAsync(B->tiles_h.ptr, B->host_th.data(), sizeof(Tile) * cnt[0], hipMemcpyHostToDevice, st));
+  if (cnt[1]) HIPCHK(hipMemcpyAsync(B->tiles_f.ptr, B->host_tf.data(), sizeof(Tile) * cnt[1], hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(B->counts.ptr, cnt, sizeof(cnt), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return MFQ_OK;
+}
+
 template <typename S, typename SX>
 int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
   const double tol2 = P->tol * P->tol;
@@ -430,6 +491,7 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
   const double delta2 = delta * delta;
   const int n_lat = (int)B->hs.size();
   CgScalars* sc = (CgScalars*)B->sc.ptr;
+  if (int rl = batch_relist(B, true, st)) return rl;
 
   // x = 0, r = b, p = r
   for (int i = 0; i < n_lat; ++i) {
@@ -444,11 +506,9 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
   HIPCHK(bvec<S, SX>(B, BV_RESTART, 0, st));
 
   auto iteration = [&](hipStream_t s) -> int {
-    HIPCHK(bhop<S, SX>(B, BM_D, 0, 0, s));
-    HIPCHK(bhop<S, SX>(B, BM_D, 1, 0, s));
+    HIPCHK(bhop<S, SX>(B, BM_D, 0, s));
     HIPCHK(bfin(B, FI_ALPHA, FIN_ALPHA, tol2, delta2, s));
-    HIPCHK(bhop<S, SX>(B, BM_CG, 0, 2, s));
-    HIPCHK(bhop<S, SX>(B, BM_CG, 1, 2, s));
+    HIPCHK(bhop<S, SX>(B, BM_CG, 2, s));
     HIPCHK(bfin(B, FI_BETA, FIN_BETA, tol2, delta2, s));
     HIPCHK(bvec<S, SX>(B, BV_XPAY, 0, s));
     return MFQ_OK;
@@ -456,10 +516,8 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
   // per-RHS reliable update over the RHS the mode covers
   auto reliable_update = [&](int mode) -> int {
     HIPCHK(bvec<S, SX>(B, BV_FOLD, mode, st));
-    HIPCHK(bhop<S, SX>(B, BM_D64, 0, -1, st, mode));
-    HIPCHK(bhop<S, SX>(B, BM_D64, 1, -1, st, mode));
-    HIPCHK(bhop<S, SX>(B, BM_RES, 0, 0, st, mode));
-    HIPCHK(bhop<S, SX>(B, BM_RES, 1, 0, st, mode));
+    HIPCHK(bhop<S, SX>(B, BM_D64, -1, st, mode));
+    HIPCHK(bhop<S, SX>(B, BM_RES, 0, st, mode));
     HIPCHK(bfin(B, FI_TRUE, mode == UPD_ALL ? FIN_TRUE : FIN_TRUE_FLAGGED, tol2, delta2, st));
     HIPCHK(bvec<S, SX>(B, BV_RESTART, 0, st));
     return MFQ_OK;
@@ -524,6 +582,7 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
       rho_prev[r] = s.state == ST_ACTIVE ? s.rho : 0.0;
     }
     if (all_done) break;
+    if (int rl = batch_relist(B, false, st)) return rl;
     if (need_update && ++n_updates > max_updates) {
       // reliable updates without iteration progress: stop (bounded loop)
       HIPCHK(hipMemcpyAsync(B->host_sc, sc, sizeof(CgScalars) * B->total, hipMemcpyDeviceToHost, st));
@@ -576,6 +635,7 @@ void mfq_batch_destroy(mfq_batch* B) {
   release(B->lats);
   release(B->tiles_h);
   release(B->tiles_f);
+  release(B->counts);
   for (int k = 0; k < 4; ++k) release(B->items[k]);
   release(B->sc);
   if (B->host_sc) (void)hipHostFree(B->host_sc);

@@ -81,9 +81,44 @@ __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
   if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
 }
 
+// Both parities, time sweep: workgroup tile = (time chunk, block of sb
+// spatial sites); each thread walks the tc time slices of its spatial site, so
+// the input it reads at t + 1 is its self term at t + 1 and its backward time
+// neighbour at t + 2 (short reuse distances in the XCD's L2 instead of a whole
+// time slice), and the threads of a wavefront cover consecutive x (both
+// parities) of one time slice at every step.
+template <int EPI, typename S, typename SX>
+__global__ __launch_bounds__(512) void hop_sweep_kernel(HopArgs<S, SX> a, int tc, int nsb) {
+  const int tile = tile_index(a.xcd);
+  const int chunk = tile / nsb;
+  const int sigma = (tile - chunk * nsb) * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y * blockDim.y + threadIdx.y;
+  const Geom& g = a.g;
+  double alpha = 0.0;
+  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r);
+  bool active = sigma < g.lx * g.ly * g.lz && r < a.n_rhs;
+  if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
+  double red = 0.0;
+  if (active) {
+    Coords c;
+    c.x = sigma % g.lx;
+    const int yz = sigma / g.lx;
+    c.y = yz % g.ly;
+    c.z = yz / g.ly;
+    const int t0 = chunk * tc;
+    const int t1 = t0 + tc < g.td ? t0 + tc : g.td;
+    for (c.t = t0; c.t < t1; ++c.t) {
+      const int par = (c.x + c.y + c.z + c.t + g.t0) & 1;
+      red += hop_site<EPI>(a, par, half_index(g, c.x, c.y, c.z, c.t), c, r, alpha);
+    }
+  }
+  if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
+}
+
 Shape default_shape(int n_rhs) {
   Shape sh;
   sh.xcd = 0;
+  sh.tc = 0;
   if (n_rhs <= 1) {
     sh.sb = 256;
     sh.nr = 1;
@@ -98,8 +133,19 @@ Shape default_shape(int n_rhs) {
 }
 
 int hop_grid_x(const Geom& g, Shape sh, int par) {
+  if (par == 2 && sh.tc > 0)
+    return ((g.lx * g.ly * g.lz + sh.sb - 1) / sh.sb) * ((g.td + sh.tc - 1) / sh.tc);
   const int per_parity = (g.vh + sh.sb - 1) / sh.sb;
   return par == 2 ? 2 * per_parity : per_parity;
+}
+
+int max_hop_blocks(const Geom& g) {
+  int m = 2 * ((g.vh + 63) / 64);
+  for (int tc = 2; tc <= 16; tc *= 2) {
+    const int b = ((g.lx * g.ly * g.lz + 63) / 64) * ((g.td + tc - 1) / tc);
+    if (b > m) m = b;
+  }
+  return m;
 }
 
 template <typename S, typename SX>
@@ -108,6 +154,24 @@ hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st
   dim3 grid(hop_grid_x(a.g, sh, a.par), (a.n_rhs + sh.nr - 1) / sh.nr);
   HopArgs<S, SX> b = a;
   b.xcd = sh.xcd;
+  if (a.par == 2 && sh.tc > 0) {
+    const int nsb = (a.g.lx * a.g.ly * a.g.lz + sh.sb - 1) / sh.sb;
+    switch (epi) {
+      case EPI_HOP: hipLaunchKernelGGL((hop_sweep_kernel<EPI_HOP, S, SX>), grid, block, 0, st, b, sh.tc, nsb); break;
+      case EPI_D: hipLaunchKernelGGL((hop_sweep_kernel<EPI_D, S, SX>), grid, block, 0, st, b, sh.tc, nsb); break;
+      case EPI_CGUPD:
+        hipLaunchKernelGGL((hop_sweep_kernel<EPI_CGUPD, S, SX>), grid, block, 0, st, b, sh.tc, nsb);
+        break;
+      case EPI_RES:
+        if constexpr (sizeof(S) == 8) {
+          hipLaunchKernelGGL((hop_sweep_kernel<EPI_RES, S, SX>), grid, block, 0, st, b, sh.tc, nsb);
+          break;
+        }
+        return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (epi) {
     case EPI_HOP: hipLaunchKernelGGL((hop_kernel<EPI_HOP, S, SX>), grid, block, 0, st, b); break;
     case EPI_D: hipLaunchKernelGGL((hop_kernel<EPI_D, S, SX>), grid, block, 0, st, b); break;

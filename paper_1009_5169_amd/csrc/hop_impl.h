@@ -52,6 +52,13 @@ __device__ __forceinline__ void block_partial(double v, double* part, int n_rhs,
   __syncthreads();
 }
 
+// Where the hopping term reads its input spinors.
+template <typename S, typename T>
+struct PlainSrc {
+  Field<S> f;
+  __device__ __forceinline__ void load(int r, int par, int s, Spinor<T>& o) const { load_spinor(f, r, par, s, o); }
+};
+
 // One direction mu of the hopping term: forward hop from n+mu through U_mu(n),
 // backward hop from n-mu through U_mu(n-mu)^+.  sgf / sgb are the projector
 // signs (-1 / +1 for H, +1 / -1 for H^+).  The time boundary is folded into a
@@ -59,9 +66,9 @@ __device__ __forceinline__ void block_partial(double v, double* part, int n_rhs,
 // antiperiodic wrap) on a neighbour index that always stays inside the
 // lattice, so the loads of every direction are unconditional and can be
 // issued together.
-template <int MU, typename S, typename SX, typename T>
-__device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, int par, const Coords& c, int s, int r,
-                                        T sgf, T sgb, Spinor<T>& acc) {
+template <int MU, typename S, typename SX, typename T, typename Src>
+__device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Src& src, int par, const Coords& c, int s,
+                                        int r, T sgf, T sgb, Spinor<T>& acc) {
   const Geom& g = a.g;
   const int po = 1 - par;
   int xf = c.x, yf = c.y, zf = c.z, tf = c.t;
@@ -93,9 +100,9 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, int par, const 
   const int sbk = half_index(g, xb, yb, zb, tb);
   Spinor<T> nf, nb;
   cpx<T> uf[9], ub[9];
-  load_spinor(a.in, r, po, sf, nf);
+  src.load(r, po, sf, nf);
   load_link(a.links, par, MU, s, uf);
-  load_spinor(a.in, r, po, sbk, nb);
+  src.load(r, po, sbk, nb);
   load_link(a.links, po, MU, sbk, ub);
   {  // forward
     cpx<T> h0[3], h1[3];
@@ -187,19 +194,20 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
 // epilogue (alpha is the CG step length, used by EPI_CGUPD); returns the value
 // this site contributes to the partial sum.
 template <int EPI, typename S, typename SX>
-__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int s, int r, double al) {
+__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
+                                           double al) {
   using T = typename Compute<S>::T;
   double red = 0.0;
   Spinor<T> acc;
   zero(acc);
-  const Coords c = site_coords(a.g, s, par);
   const T sgf = a.dagger ? (T)1 : (T)-1;
   const T sgb = -sgf;
-  hop_dir<0>(a, par, c, s, r, sgf, sgb, acc);
-  hop_dir<1>(a, par, c, s, r, sgf, sgb, acc);
-  hop_dir<2>(a, par, c, s, r, sgf, sgb, acc);
-  hop_dir<3>(a, par, c, s, r, sgf, sgb, acc);
   const T b = (T)a.coef;
+  PlainSrc<S, T> src{a.in};
+  hop_dir<0>(a, src, par, c, s, r, sgf, sgb, acc);
+  hop_dir<1>(a, src, par, c, s, r, sgf, sgb, acc);
+  hop_dir<2>(a, src, par, c, s, r, sgf, sgb, acc);
+  hop_dir<3>(a, src, par, c, s, r, sgf, sgb, acc);
   if constexpr (EPI == EPI_HOP) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc.v[k] = b * acc.v[k];
@@ -244,6 +252,11 @@ __device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int
     red = snorm2(bb);
   }
   return red;
+}
+
+template <int EPI, typename S, typename SX>
+__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int s, int r, double al) {
+  return hop_site<EPI>(a, par, s, site_coords(a.g, s, par), r, al);
 }
 
 }  // namespace mfq

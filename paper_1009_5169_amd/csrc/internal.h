@@ -72,7 +72,13 @@ struct Shape {
   int sb;   // sites per workgroup (multiple of 64)
   int nr;   // right-hand sides per workgroup
   int xcd;  // remap workgroups so each XCD walks a contiguous chunk of sites
+  int tc;   // both-parity launches: 0, or each thread sweeps tc time slices of
+            // one spatial site (sb spatial sites per workgroup)
 };
+
+// Upper bound on the workgroups along x of any hopping launch (partial-sum
+// capacity per RHS).
+int max_hop_blocks(const Geom& g);
 
 Shape default_shape(int n_rhs);
 // Workgroups along x of a hopping launch (par 0 / 1, or 2 for both parities).

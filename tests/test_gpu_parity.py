@@ -149,6 +149,38 @@ def test_solve_matches_oracle(case, prec):
     lat.close()
 
 
+BC_CODE = {"sf": 0, "periodic": 1, "antiperiodic": 2}
+PREC_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(64, 1, 0, 2), (64, 3, 1, 4), (128, 2, 0, 8), (64, 1, 1, 16), (128, 1, 0, 0),
+                                   (64, 3, 1, 0)], ids=lambda s: "sb%d_nr%d_xcd%d_tc%d" % s)
+def test_forced_launch_shapes_match_oracle(tmp_path, monkeypatch, shape, prec):
+    """Every launch shape the autotuner may pick, forced through the tuning
+    cache: plain and time-sweep both-parity kernels (sweep lengths that do not
+    divide the 9 dynamical time slices), with and without the XCD remap, give
+    solutions that meet the oracle's residual and error bound."""
+    dims, bc, kappa, n, tol = (4, 6, 2, 10), "sf", 0.13, 3, 1e-10
+    key = "gfx950 %d %d %d %d %d %d %d" % (dims + (BC_CODE[bc], n, PREC_BYTES[prec]))
+    cache = tmp_path / "tune.txt"
+    cache.write_text(key + "|%d %d %d %d\n" % shape)
+    monkeypatch.setenv("MFQ_AUTOTUNE_CACHE", str(cache))
+    _, lat, d = make(dims, bc, kappa, 0.4, 1100)
+    b = synth.gaussian_spinors(dims, bc, n, 2100)
+    x, stats, rc = lat.solve(to_dev(b), tol=tol, prec=prec, max_iter=5000)
+    assert tuple(lat.hop_shape(prec, n)) == shape
+    assert rc == 0, stats
+    x = to_host(x)
+    for i in range(n):
+        res = np.linalg.norm(b[i:i + 1] - d.DdagD(x[i:i + 1])) / np.linalg.norm(b[i])
+        assert res <= tol * 1.05, (i, res)
+    x_ref, _ = solvers.cg_normal(d, b, 1e-14)
+    c = _cond(d, b)
+    assert rel(x, x_ref) <= c * (tol + 1e-14) + 1e-14, (rel(x, x_ref), c)
+    lat.close()
+
+
 def test_solve_fp64_tight_matches_oracle_to_1e12():
     """On the 4^4 SF case (cond ~ 180) an FP64 solve to 1e-12/cond reproduces
     the oracle's solution to 1e-12."""
