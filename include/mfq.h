@@ -244,12 +244,13 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
  * fixed default shape.  Changing the setting drops tuned shapes and graphs. */
 int mfq_set_autotune(mfq_handle* h, int on);
 
-/* The shape the inner solver uses for (precision, n_rhs): shape4 (host, 4
+/* The shape the inner solver uses for (precision, n_rhs): shape5 (host, 5
  * ints) receives {sites per workgroup, RHS per workgroup, XCD remap flag,
  * time-sweep length (0: one site per thread; else each thread walks that many
  * time slices of one spatial site, sites per workgroup then counting spatial
- * sites)}. */
-int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape4);
+ * sites), direction split (0, or 2 / 4 wavefronts sharing the 4 directions of
+ * 64 sites of one RHS)}. */
+int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape5);
 
 void mfq_destroy(mfq_handle* h);
 

@@ -197,15 +197,18 @@ bool tune_cache_lookup(mfq_handle* h, int n, int prec, Shape* out) {
   char line[256];
   bool found = false;
   while (fgets(line, sizeof(line), f)) {
-    int sb, nr, xcd, tc;
+    int sb, nr, xcd, tc, ds;
     const char* bar = strchr(line, '|');
     if (!bar || std::string(line, bar - line) != key) continue;
-    if (sscanf(bar + 1, "%d %d %d %d", &sb, &nr, &xcd, &tc) == 4 && sb >= 64 && sb % 64 == 0 && nr >= 1 &&
-        sb * nr <= 512 && (tc == 0 || tc == 2 || tc == 4 || tc == 8 || tc == 16)) {
+    if (sscanf(bar + 1, "%d %d %d %d %d", &sb, &nr, &xcd, &tc, &ds) == 5 && sb >= 64 && sb % 64 == 0 && nr >= 1 &&
+        sb * nr <= 512 && (tc == 0 || tc == 2 || tc == 4 || tc == 8 || tc == 16) &&
+        (ds == 0 || ((ds == 2 || ds == 4) && sb == 64 && ds * nr <= 8 && tc == 0 &&
+                     nr * (ds - 1) * 24 * 64 * (prec == 8 ? 8 : 4) <= 65536))) {
       out->sb = sb;
       out->nr = nr;
       out->xcd = xcd ? 1 : 0;
       out->tc = tc;
+      out->ds = ds;
       found = true;
     }
   }
@@ -235,17 +238,22 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
       for (int tc = 0; tc <= 4; tc += 4) {  // the time sweep measured slower so far: one candidate
         if (tc >= 2 * h->g.td) continue;  // one chunk already covers the time extent
         for (int xcd = 0; xcd < 2; ++xcd) {
-          Shape sh{sb, nr, xcd, tc};
-          for (int i = 0; i < 2; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
-          HIPCHK(hipEventRecord(h->ev0, st));
-          for (int i = 0; i < 10; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
-          HIPCHK(hipEventRecord(h->ev1, st));
-          HIPCHK(hipEventSynchronize(h->ev1));
-          float ms = 0.f;
-          HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-          if (ms < best * 0.97f) {  // prefer earlier (simpler) shapes on near ties
-            best = ms;
-            best_sh = sh;
+          for (int ds = 0; ds <= 4; ds += 2) {
+            // split: 64 sites x nr RHS, ds * nr waves, partial hopping terms in LDS
+            if (ds && (sb != 64 || ds * nr > 8 || tc || nr * (ds - 1) * 24 * 64 * (prec == 8 ? 8 : 4) > 65536))
+              continue;
+            Shape sh{sb, nr, xcd, tc, ds};
+            for (int i = 0; i < 2; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+            HIPCHK(hipEventRecord(h->ev0, st));
+            for (int i = 0; i < 10; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+            HIPCHK(hipEventRecord(h->ev1, st));
+            HIPCHK(hipEventSynchronize(h->ev1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+            if (ms < best * 0.97f) {  // prefer earlier (simpler) shapes on near ties
+              best = ms;
+              best_sh = sh;
+            }
           }
         }
       }
@@ -254,8 +262,8 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
   h->tuned.push_back({n, prec, best_sh, best * 100.f});
   if (const char* path = getenv("MFQ_AUTOTUNE_CACHE")) {
     if (FILE* f = fopen(path, "a")) {
-      fprintf(f, "%s|%d %d %d %d\n", tune_key(h, n, prec).c_str(), best_sh.sb, best_sh.nr, best_sh.xcd,
-              best_sh.tc);
+      fprintf(f, "%s|%d %d %d %d %d\n", tune_key(h, n, prec).c_str(), best_sh.sb, best_sh.nr, best_sh.xcd,
+              best_sh.tc, best_sh.ds);
       fclose(f);
     }
   }
@@ -381,7 +389,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
                                   (uintptr_t)in.r.data, (uintptr_t)in.p.data, (uintptr_t)in.t.data,
                                   (uintptr_t)in.x.data, (uintptr_t)in.L.data, (uintptr_t)w.part.ptr,
                                   (uintptr_t)sc, bits(tol2), bits(delta2), (uintptr_t)sh.sb,
-                                  (uintptr_t)sh.nr, (uintptr_t)sh.xcd, (uintptr_t)sh.tc};
+                                  (uintptr_t)sh.nr, (uintptr_t)sh.xcd, (uintptr_t)sh.tc, (uintptr_t)sh.ds};
     GraphEntry* hit = nullptr;
     for (auto& e : h->graphs)
       if (e.key == key) hit = &e;
@@ -775,15 +783,16 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
   }
 }
 
-int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape4) {
-  if (!h || !shape4) return fail(MFQ_ERR_ARG, "NULL argument");
+int mfq_hop_shape(mfq_handle* h, int prec, int n_rhs, int* shape5) {
+  if (!h || !shape5) return fail(MFQ_ERR_ARG, "NULL argument");
   Shape sh = default_shape(n_rhs);
   for (auto& e : h->tuned)
     if (e.n == n_rhs && e.prec == (prec == 0 ? 8 : prec == 1 ? 4 : 2)) sh = e.sh;
-  shape4[0] = sh.sb;
-  shape4[1] = sh.nr;
-  shape4[2] = sh.xcd;
-  shape4[3] = sh.tc;
+  shape5[0] = sh.sb;
+  shape5[1] = sh.nr;
+  shape5[2] = sh.xcd;
+  shape5[3] = sh.tc;
+  shape5[4] = sh.ds;
   return MFQ_OK;
 }
 

@@ -33,10 +33,10 @@ __device__ __forceinline__ int tile_index(int remap) {
 // breakdown (p^+ A p <= 0) alpha is 0 in every workgroup and workgroup 0
 // marks the RHS for a true-residual check.
 template <typename S, typename SX>
-__device__ __forceinline__ double cg_alpha(const HopArgs<S, SX>& a, int r) {
+__device__ __forceinline__ double cg_alpha(const HopArgs<S, SX>& a, int r, int row, bool leader) {
   if (!a.apart) return r < a.n_rhs ? a.sc[r].alpha : 0.0;
   __shared__ double s_alpha[8];
-  if (threadIdx.x < 64) {
+  if (leader) {
     double v = 0.0;
     if (r < a.n_rhs)
       for (int j = threadIdx.x; j < a.anblk; j += 64) v += a.apart[(long)r * a.anblk + j];
@@ -50,11 +50,11 @@ __device__ __forceinline__ double cg_alpha(const HopArgs<S, SX>& a, int r) {
           a.sc[r].state = ST_CHECK;
         }
       }
-      s_alpha[threadIdx.y] = al;
+      s_alpha[row] = al;
     }
   }
   __syncthreads();
-  return s_alpha[threadIdx.y];
+  return s_alpha[row];
 }
 
 // With both parities in one launch (par == 2) consecutive tiles alternate
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
   }
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
   double alpha = 0.0;
-  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r);
+  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r, threadIdx.y, threadIdx.x < 64);
   bool active = s < a.g.vh && r < a.n_rhs;
   if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
   const double red = active ? hop_site<EPI>(a, par, s, r, alpha) : 0.0;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(512) void hop_sweep_kernel(HopArgs<S, SX> a, int tc
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
   const Geom& g = a.g;
   double alpha = 0.0;
-  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r);
+  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r, threadIdx.y, threadIdx.x < 64);
   bool active = sigma < g.lx * g.ly * g.lz && r < a.n_rhs;
   if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
   double red = 0.0;
@@ -115,10 +115,77 @@ __global__ __launch_bounds__(512) void hop_sweep_kernel(HopArgs<S, SX> a, int tc
   if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
 }
 
+// Direction split: a workgroup of DS x nr wavefronts covers 64 sites of nr
+// RHS; wavefront w of a row computes directions [4w/DS, 4(w+1)/DS) of every
+// site, the partial sums meet in LDS and the row's wavefront 0 applies the
+// epilogue.  Each thread's chain of dependent loads is DS times shorter and a
+// thread holds fewer registers, which is what bounds small lattices (one
+// wavefront per CU or fewer) and helps latency hiding on large ones.
+template <int EPI, int DS, typename S, typename SX>
+__global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
+  using T = typename Compute<S>::T;
+  extern __shared__ __align__(16) unsigned char split_lds[];  // [rows][DS - 1][24][64] of T
+  T(*lds)[DS - 1][24][64] = reinterpret_cast<T(*)[DS - 1][24][64]>(split_lds);
+  const int tile = tile_index(a.xcd);
+  int par = a.par;
+  int s;
+  if (par == 2) {
+    par = tile & 1;
+    s = (tile >> 1) * 64 + threadIdx.x;
+  } else {
+    s = tile * 64 + threadIdx.x;
+  }
+  const int row = threadIdx.y / DS, w = threadIdx.y - row * DS;
+  const int r = blockIdx.y * (blockDim.y / DS) + row;
+  double alpha = 0.0;
+  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r, row, w == 0);
+  bool active = s < a.g.vh && r < a.n_rhs;
+  if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
+  Spinor<T> acc;
+  zero(acc);
+  if (active) {
+    const Coords c = site_coords(a.g, s, par);
+    if constexpr (DS == 2) {
+      if (w == 0) hop_dirs<0, 2>(a, par, s, c, r, acc);
+      else hop_dirs<2, 4>(a, par, s, c, r, acc);
+    } else {
+      if (w == 0) hop_dirs<0, 1>(a, par, s, c, r, acc);
+      else if (w == 1) hop_dirs<1, 2>(a, par, s, c, r, acc);
+      else if (w == 2) hop_dirs<2, 3>(a, par, s, c, r, acc);
+      else hop_dirs<3, 4>(a, par, s, c, r, acc);
+    }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      lds[row][w - 1][2 * k][threadIdx.x] = acc.v[k].re;
+      lds[row][w - 1][2 * k + 1][threadIdx.x] = acc.v[k].im;
+    }
+  }
+  __syncthreads();
+  if (w != 0) return;
+  double red = 0.0;
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < DS - 1; ++q)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        acc.v[k].re += lds[row][q][2 * k][threadIdx.x];
+        acc.v[k].im += lds[row][q][2 * k + 1][threadIdx.x];
+      }
+    red = hop_epilogue<EPI>(a, par, s, r, alpha, acc);
+  }
+  if (a.part) {
+    red = wave_sum(red);
+    if (threadIdx.x == 0 && r < a.n_rhs) a.part[(long)r * gridDim.x + blockIdx.x] = red;
+  }
+}
+
 Shape default_shape(int n_rhs) {
   Shape sh;
   sh.xcd = 0;
   sh.tc = 0;
+  sh.ds = 0;
   if (n_rhs <= 1) {
     sh.sb = 256;
     sh.nr = 1;
@@ -133,7 +200,8 @@ Shape default_shape(int n_rhs) {
 }
 
 int hop_grid_x(const Geom& g, Shape sh, int par) {
-  if (par == 2 && sh.tc > 0)
+  if (sh.ds > 1) sh.sb = 64;
+  if (par == 2 && sh.tc > 0 && sh.ds <= 1)
     return ((g.lx * g.ly * g.lz + sh.sb - 1) / sh.sb) * ((g.td + sh.tc - 1) / sh.tc);
   const int per_parity = (g.vh + sh.sb - 1) / sh.sb;
   return par == 2 ? 2 * per_parity : per_parity;
@@ -150,10 +218,39 @@ int max_hop_blocks(const Geom& g) {
 
 template <typename S, typename SX>
 hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st) {
-  dim3 block(sh.sb, sh.nr);
-  dim3 grid(hop_grid_x(a.g, sh, a.par), (a.n_rhs + sh.nr - 1) / sh.nr);
   HopArgs<S, SX> b = a;
   b.xcd = sh.xcd;
+  if (sh.ds == 2 || sh.ds == 4) {
+    Shape s64 = sh;
+    s64.sb = 64;
+    s64.tc = 0;
+    const dim3 grid(hop_grid_x(a.g, s64, a.par), (a.n_rhs + sh.nr - 1) / sh.nr), block(64, sh.ds * sh.nr);
+    using T = typename Compute<S>::T;
+    const size_t lds_bytes = (size_t)sh.nr * (sh.ds - 1) * 24 * 64 * sizeof(T);
+#define MFQ_SPLIT(E)                                                                    \
+  do {                                                                                  \
+    if (sh.ds == 2)                                                                     \
+      hipLaunchKernelGGL((hop_split_kernel<E, 2, S, SX>), grid, block, lds_bytes, st, b); \
+    else                                                                                \
+      hipLaunchKernelGGL((hop_split_kernel<E, 4, S, SX>), grid, block, lds_bytes, st, b); \
+  } while (0)
+    switch (epi) {
+      case EPI_HOP: MFQ_SPLIT(EPI_HOP); break;
+      case EPI_D: MFQ_SPLIT(EPI_D); break;
+      case EPI_CGUPD: MFQ_SPLIT(EPI_CGUPD); break;
+      case EPI_RES:
+        if constexpr (sizeof(S) == 8) {
+          MFQ_SPLIT(EPI_RES);
+          break;
+        }
+        return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
+#undef MFQ_SPLIT
+    return hipGetLastError();
+  }
+  dim3 block(sh.sb, sh.nr);
+  dim3 grid(hop_grid_x(a.g, sh, a.par), (a.n_rhs + sh.nr - 1) / sh.nr);
   if (a.par == 2 && sh.tc > 0) {
     const int nsb = (a.g.lx * a.g.ly * a.g.lz + sh.sb - 1) / sh.sb;
     switch (epi) {

@@ -190,24 +190,26 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
 }
 
 
-// The hopping term at output site s of parity par for RHS r, followed by the
-// epilogue (alpha is the CG step length, used by EPI_CGUPD); returns the value
-// this site contributes to the partial sum.
-template <int EPI, typename S, typename SX>
-__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
-                                           double al) {
-  using T = typename Compute<S>::T;
-  double red = 0.0;
-  Spinor<T> acc;
-  zero(acc);
+// Directions [MU0, MU1) of the hopping term at output site s, accumulated into acc.
+template <int MU0, int MU1, typename S, typename SX, typename T>
+__device__ __forceinline__ void hop_dirs(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
+                                         Spinor<T>& acc) {
   const T sgf = a.dagger ? (T)1 : (T)-1;
   const T sgb = -sgf;
-  const T b = (T)a.coef;
   PlainSrc<S, T> src{a.in};
-  hop_dir<0>(a, src, par, c, s, r, sgf, sgb, acc);
-  hop_dir<1>(a, src, par, c, s, r, sgf, sgb, acc);
-  hop_dir<2>(a, src, par, c, s, r, sgf, sgb, acc);
-  hop_dir<3>(a, src, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 0 && 0 < MU1) hop_dir<0>(a, src, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 1 && 1 < MU1) hop_dir<1>(a, src, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 2 && 2 < MU1) hop_dir<2>(a, src, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 3 && 3 < MU1) hop_dir<3>(a, src, par, c, s, r, sgf, sgb, acc);
+}
+
+// The epilogue applied to the complete hopping term acc at output site s;
+// returns the value this site contributes to the partial sum.
+template <int EPI, typename S, typename SX, typename T>
+__device__ __forceinline__ double hop_epilogue(const HopArgs<S, SX>& a, int par, int s, int r, double al,
+                                               Spinor<T>& acc) {
+  double red = 0.0;
+  const T b = (T)a.coef;
   if constexpr (EPI == EPI_HOP) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc.v[k] = b * acc.v[k];
@@ -252,6 +254,18 @@ __device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int
     red = snorm2(bb);
   }
   return red;
+}
+
+// The hopping term at output site s of parity par for RHS r, followed by the
+// epilogue (alpha is the CG step length, used by EPI_CGUPD).
+template <int EPI, typename S, typename SX>
+__device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
+                                           double al) {
+  using T = typename Compute<S>::T;
+  Spinor<T> acc;
+  zero(acc);
+  hop_dirs<0, 4>(a, par, s, c, r, acc);
+  return hop_epilogue<EPI>(a, par, s, r, al, acc);
 }
 
 template <int EPI, typename S, typename SX>

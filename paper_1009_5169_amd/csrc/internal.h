@@ -74,6 +74,8 @@ struct Shape {
   int xcd;  // remap workgroups so each XCD walks a contiguous chunk of sites
   int tc;   // both-parity launches: 0, or each thread sweeps tc time slices of
             // one spatial site (sb spatial sites per workgroup)
+  int ds;   // 0, or 2 / 4: the 4 directions of a site split over that many
+            // wavefronts of one workgroup (64 sites x nr RHS, ds * nr <= 8)
 };
 
 // Upper bound on the workgroups along x of any hopping launch (partial-sum

@@ -154,17 +154,19 @@ PREC_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("shape", [(64, 1, 0, 2), (64, 3, 1, 4), (128, 2, 0, 8), (64, 1, 1, 16), (128, 1, 0, 0),
-                                   (64, 3, 1, 0)], ids=lambda s: "sb%d_nr%d_xcd%d_tc%d" % s)
+@pytest.mark.parametrize("shape", [(64, 1, 0, 2, 0), (64, 3, 1, 4, 0), (128, 2, 0, 8, 0), (64, 1, 1, 16, 0),
+                                   (128, 1, 0, 0, 0), (64, 3, 1, 0, 0), (64, 1, 0, 0, 2), (64, 1, 1, 0, 4),
+                                   (64, 3, 0, 0, 2), (64, 2, 1, 0, 2)],
+                         ids=lambda s: "sb%d_nr%d_xcd%d_tc%d_ds%d" % s)
 def test_forced_launch_shapes_match_oracle(tmp_path, monkeypatch, shape, prec):
     """Every launch shape the autotuner may pick, forced through the tuning
-    cache: plain and time-sweep both-parity kernels (sweep lengths that do not
-    divide the 9 dynamical time slices), with and without the XCD remap, give
-    solutions that meet the oracle's residual and error bound."""
+    cache: plain, time-sweep (sweep lengths that do not divide the 9 dynamical
+    time slices) and direction-split both-parity kernels, with and without the
+    XCD remap, give solutions that meet the oracle's residual and error bound."""
     dims, bc, kappa, n, tol = (4, 6, 2, 10), "sf", 0.13, 3, 1e-10
     key = "gfx950 %d %d %d %d %d %d %d" % (dims + (BC_CODE[bc], n, PREC_BYTES[prec]))
     cache = tmp_path / "tune.txt"
-    cache.write_text(key + "|%d %d %d %d\n" % shape)
+    cache.write_text(key + "|%d %d %d %d %d\n" % shape)
     monkeypatch.setenv("MFQ_AUTOTUNE_CACHE", str(cache))
     _, lat, d = make(dims, bc, kappa, 0.4, 1100)
     b = synth.gaussian_spinors(dims, bc, n, 2100)
