@@ -63,6 +63,16 @@ def measured_traffic(prec: str, n_rhs: int):
     return int(round((fetch + write) * 1024))
 
 
+def kernel_name(prec: str, shape) -> str:
+    """The hopping kernel a launch shape (sb, nr, xcd, tc, ds) selects."""
+    sb, nr, xcd, tc, ds = shape
+    if ds:
+        return f"hop_split_kernel<EPI_D, {ds}, {prec}> (both parities)"
+    if tc:
+        return f"hop_sweep_kernel<EPI_D, {prec}> (both parities, {tc} time slices per thread)"
+    return f"hop_kernel<EPI_D, {prec}> (both parities)"
+
+
 def hop_bytes_per_site_rhs(prec: str, n_rhs: int) -> float:
     """Algorithmic HBM bytes of the timed hopping kernel (D epilogue, both
     parities in one launch, input = self field) per lattice site per RHS: the
@@ -138,13 +148,14 @@ def main():
     # timed with HIP events on its stream
     n = p.n_rhs
     hop_ms = lat.time_hop(args.prec, n, iters=200)
+    shape = lat.hop_shape(args.prec, n)
     vd = p.dims[0] * p.dims[1] * p.dims[2] * (p.dims[3] - 1)
     per_launch = hop_bytes_per_site_rhs(args.prec, n) * vd * n
     achieved = per_launch / (hop_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.prec, n),
-                "kernel": f"hop_kernel<EPI_D,{args.prec}> (both parities)", "launch_us": round(hop_ms * 1e3, 3),
-                "shape": list(lat.hop_shape(args.prec, n)),
+                "kernel": kernel_name(args.prec, shape), "launch_us": round(hop_ms * 1e3, 3),
+                "shape": list(shape),
                 "algorithmic_bytes_per_launch": int(per_launch)}
 
     # solve-only times on the same GPU: this precision and plain FP64 CG

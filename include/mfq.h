@@ -240,7 +240,9 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
  * default).  The first solve (or mfq_time_hop) for a given (n_rhs, precision)
  * times candidate (sites per workgroup, RHS per workgroup, XCD remap) shapes
  * with HIP events and keeps the fastest; MFQ_AUTOTUNE_CACHE, if set, names a
- * text file where choices are stored and looked up.  Turning it off uses a
+ * text file where choices are stored and looked up; if it is not set, the
+ * table tune_gfx950.txt next to the library (shapes tuned on MI355X for the
+ * shipped workloads) is looked up and nothing is written.  Turning it off uses a
  * fixed default shape.  Changing the setting drops tuned shapes and graphs. */
 int mfq_set_autotune(mfq_handle* h, int on);
 

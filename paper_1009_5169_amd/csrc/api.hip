@@ -1,6 +1,7 @@
 // C ABI of libmfq: handle management, argument validation, the batched
 // multi-RHS CG driver (FP64, FP32 with FP64 reliable updates, FP16 with FP64
 // defect correction), the blocked force of Alg. 2, and kernel timing.
+#include <dlfcn.h>
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -183,14 +184,26 @@ std::string tune_key(mfq_handle* h, int n, int prec) {
   return buf;
 }
 
+// The shipped table of tuned shapes for gfx950 next to the library
+// (tune_gfx950.txt), read when MFQ_AUTOTUNE_CACHE is not set.
+std::string default_tune_table() {
+  Dl_info info;
+  if (!dladdr((void*)&default_tune_table, &info) || !info.dli_fname) return std::string();
+  std::string lib(info.dli_fname);
+  const size_t slash = lib.rfind('/');
+  return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tune_gfx950.txt";
+}
+
 bool tune_cache_lookup(mfq_handle* h, int n, int prec, Shape* out) {
   for (auto& e : h->tuned)
     if (e.n == n && e.prec == prec) {
       *out = e.sh;
       return true;
     }
-  const char* path = getenv("MFQ_AUTOTUNE_CACHE");
-  if (!path) return false;
+  const char* env = getenv("MFQ_AUTOTUNE_CACHE");
+  const std::string table = env ? std::string(env) : default_tune_table();
+  if (table.empty()) return false;
+  const char* path = table.c_str();
   FILE* f = fopen(path, "r");
   if (!f) return false;
   const std::string key = tune_key(h, n, prec);
