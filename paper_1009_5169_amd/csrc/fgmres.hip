@@ -28,7 +28,9 @@ struct GmState {
   double yr[GM_MAXM], yi[GM_MAXM];
   double cr[GM_MAXM + 1], ci[GM_MAXM + 1];  // Gram-Schmidt coefficients of the current pass
   double bnorm2, rtrue2, wnorm;
-  int k, active, done, iters, cycles, pad;
+  double w2;   // |w|^2 before the first Gram-Schmidt pass
+  int k, active, done, iters, cycles;
+  int reorth;  // the second Gram-Schmidt pass is needed for this step
 };
 
 #define GM_LANE                                                    \
@@ -54,13 +56,26 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* part_a, d
   __syncthreads();
 }
 
-// <v_l, w> for l < nv: partials part[((r * nv + l) * nblk + blk) * 2 + {re, im}]
+// <v_l, w> for l < nv, and with `first` also |w|^2 as entry nv: partials
+// part[((r * (nv + 1) + l) * nblk + blk) * 2 + {re, im}].  The second pass
+// runs only for the RHS whose first pass asked for it (the whole workgroup
+// belongs to one RHS, so it returns together).
 __global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> V, size_t vstride, int nv,
-                                                          Field<double> w, int n_rhs, double* part) {
+                                                          Field<double> w, int n_rhs, double* part, int first,
+                                                          const GmState* st) {
   GM_LANE
+  if (!first && !st[r].reorth) return;
   Spinor<double> ww;
   if (valid) load_spinor(w, r, par, s, ww);
   const int nblk = gridDim.x;
+  if (first) {
+    double v = 0.0;
+    if (valid)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v += norm2(ww.v[k]);
+    double* base = part + (((long)r * (nv + 1) + nv) * nblk + blockIdx.x) * 2;
+    block_sum2(v, 0.0, base, base + 1);
+  }
   for (int l = 0; l < nv; ++l) {
     double re = 0.0, im = 0.0;
     if (valid) {
@@ -75,19 +90,22 @@ __global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> 
         im += d.im;
       }
     }
-    double* base = part + (((long)r * nv + l) * nblk + blockIdx.x) * 2;
+    double* base = part + (((long)r * (nv + 1) + l) * nblk + blockIdx.x) * 2;
     block_sum2(re, im, base, base + 1);
   }
 }
 
-// coefficients c_l = sum of partials; H(:, j) += c (accumulate over passes)
+// coefficients c_l = sum of partials; H(:, j) += c (accumulate over passes).
+// One wavefront per (RHS, l); the first pass also reduces |w|^2 (l = nv).
 __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int n_rhs, GmState* st, int j, int first) {
   const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (w >= n_rhs * nv) return;
-  const int r = w / nv, l = w % nv;
+  const int nl = nv + (first ? 1 : 0);
+  if (w >= n_rhs * nl) return;
+  const int r = w / nl, l = w % nl;
+  if (!first && !st[r].reorth) return;
   double re = 0.0, im = 0.0;
-  const double* p = part + ((long)r * nv + l) * nblk * 2;
+  const double* p = part + ((long)r * (nv + 1) + l) * nblk * 2;
   for (int b = lane; b < nblk; b += 64) {
     re += p[2 * b];
     im += p[2 * b + 1];
@@ -96,6 +114,10 @@ __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int 
   im = wave_sum(im);
   if (lane == 0) {
     GmState& S = st[r];
+    if (l == nv) {  // first pass: |w|^2 before the projection
+      S.w2 = re;
+      return;
+    }
     S.cr[l] = re;
     S.ci[l] = im;
     const int idx = j * (GM_MAXM + 1) + l;
@@ -109,10 +131,21 @@ __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int 
   }
 }
 
-// w -= sum_l c_l v_l
+// w -= sum_l c_l v_l.  After the first pass, workgroup 0 of each RHS decides
+// whether the second pass is needed: the projected norm |w'|^2 = |w|^2 -
+// sum |c_l|^2 below half of |w|^2 (|w'| < 0.7 |w|, Kahan's criterion) means
+// cancellation has eaten the orthogonality and the pass is repeated.  No
+// other workgroup of this launch reads the flag.
 __global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double> V, size_t vstride, int nv,
-                                                           Field<double> w, int n_rhs, const GmState* st) {
+                                                           Field<double> w, int n_rhs, GmState* st, int first) {
   GM_LANE
+  if (!first && !st[r].reorth) return;
+  if (first && blockIdx.x == 0 && threadIdx.x == 0) {
+    double c2 = 0.0;
+    for (int l = 0; l < nv; ++l) c2 += st[r].cr[l] * st[r].cr[l] + st[r].ci[l] * st[r].ci[l];
+    const double w2 = st[r].w2;
+    st[r].reorth = !(w2 - c2 > 0.49 * w2);
+  }
   if (!valid) return;
   Spinor<double> ww;
   load_spinor(w, r, par, s, ww);
@@ -382,11 +415,15 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
         HIPCHK(hipMemcpyAsync(vj(Z, j).data, vj(V, j).data, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
       }
       if ((rc = apply_a(vj(Z, j), W))) return cleanup(), rc;
-      for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-        hipLaunchKernelGGL(gm_multidot_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, part);
-        hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 1) + 3) / 4), dim3(256), 0, st, part, nblk, j + 1,
-                           n, S, j, pass == 0 ? 1 : 0);
-        hipLaunchKernelGGL(gm_multiaxpy_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, S);
+      // classical Gram-Schmidt; the second pass only where the first lost
+      // more than half of |w| (the kernels of that pass return at once for
+      // the other RHS)
+      for (int pass = 0; pass < 2; ++pass) {
+        const int first = pass == 0 ? 1 : 0;
+        hipLaunchKernelGGL(gm_multidot_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, part, first, S);
+        hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 2) + 3) / 4), dim3(256), 0, st, part, nblk, j + 1,
+                           n, S, j, first);
+        hipLaunchKernelGGL(gm_multiaxpy_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, S, first);
       }
       if ((rc = norm_finish(W, j, 0))) return cleanup(), rc;
       hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, W, vj(V, j + 1), n, S);

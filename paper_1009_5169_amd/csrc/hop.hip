@@ -27,19 +27,30 @@ __device__ __forceinline__ int tile_index(int remap) {
   return xcd * q + (xcd < rem ? xcd : rem) + (b >> 3);
 }
 
-// The CG step length for RHS row threadIdx.y: from the scalars, or, when the
+// The CG step length for RHS row `row`: from the scalars, or, when the
 // |D p|^2 partials are passed (small lattices), reduced here by the row's
-// first wavefront in the same fixed order as the finishing kernel.  On a
-// breakdown (p^+ A p <= 0) alpha is 0 in every workgroup and workgroup 0
-// marks the RHS for a true-residual check.
+// leader wavefront in the same fixed order as the finishing kernel.  Split in
+// two so that the partials' loads are issued at the start of the kernel and
+// their latency hides behind the hopping term: alpha_fetch returns this
+// lane's share, alpha_finish reduces it and broadcasts alpha through LDS (it
+// holds a workgroup barrier).  On a breakdown (p^+ A p <= 0) alpha is 0 in
+// every workgroup and workgroup 0 marks the RHS for a true-residual check.
 template <typename S, typename SX>
-__device__ __forceinline__ double cg_alpha(const HopArgs<S, SX>& a, int r, int row, bool leader) {
-  if (!a.apart) return r < a.n_rhs ? a.sc[r].alpha : 0.0;
+__device__ __forceinline__ double alpha_fetch(const HopArgs<S, SX>& a, int r, bool leader) {
+  double v = 0.0;
+  if (a.apart && leader && r < a.n_rhs)
+    for (int j = threadIdx.x; j < a.anblk; j += 64) v += a.apart[(long)r * a.anblk + j];
+  return v;
+}
+
+template <typename S, typename SX>
+__device__ __forceinline__ double alpha_finish(const HopArgs<S, SX>& a, int r, int row, bool leader, double v) {
+  if (!a.apart) {
+    __syncthreads();
+    return r < a.n_rhs ? a.sc[r].alpha : 0.0;
+  }
   __shared__ double s_alpha[8];
   if (leader) {
-    double v = 0.0;
-    if (r < a.n_rhs)
-      for (int j = threadIdx.x; j < a.anblk; j += 64) v += a.apart[(long)r * a.anblk + j];
     v = wave_sum(v);
     if (threadIdx.x == 0) {
       double al = 0.0;
@@ -73,11 +84,17 @@ __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
     s = tile * blockDim.x + threadIdx.x;
   }
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
-  double alpha = 0.0;
-  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r, threadIdx.y, threadIdx.x < 64);
+  double av = 0.0;
+  if constexpr (EPI == EPI_CGUPD) av = alpha_fetch(a, r, threadIdx.x < 64);
   bool active = s < a.g.vh && r < a.n_rhs;
   if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
-  const double red = active ? hop_site<EPI>(a, par, s, r, alpha) : 0.0;
+  using T = typename Compute<S>::T;
+  Spinor<T> acc;
+  zero(acc);
+  if (active) hop_dirs<0, 4>(a, par, s, site_coords(a.g, s, par), r, acc);
+  double alpha = 0.0;
+  if constexpr (EPI == EPI_CGUPD) alpha = alpha_finish(a, r, threadIdx.y, threadIdx.x < 64, av);
+  const double red = active ? hop_epilogue<EPI>(a, par, s, r, alpha, acc) : 0.0;
   if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
 }
 
@@ -95,7 +112,8 @@ __global__ __launch_bounds__(512) void hop_sweep_kernel(HopArgs<S, SX> a, int tc
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
   const Geom& g = a.g;
   double alpha = 0.0;
-  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r, threadIdx.y, threadIdx.x < 64);
+  if constexpr (EPI == EPI_CGUPD)
+    alpha = alpha_finish(a, r, threadIdx.y, threadIdx.x < 64, alpha_fetch(a, r, threadIdx.x < 64));
   bool active = sigma < g.lx * g.ly * g.lz && r < a.n_rhs;
   if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
   double red = 0.0;
@@ -137,8 +155,8 @@ __global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
   }
   const int row = threadIdx.y / DS, w = threadIdx.y - row * DS;
   const int r = blockIdx.y * (blockDim.y / DS) + row;
-  double alpha = 0.0;
-  if constexpr (EPI == EPI_CGUPD) alpha = cg_alpha(a, r, row, w == 0);
+  double av = 0.0;
+  if constexpr (EPI == EPI_CGUPD) av = alpha_fetch(a, r, w == 0);
   bool active = s < a.g.vh && r < a.n_rhs;
   if (active && a.sc) active = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
   Spinor<T> acc;
@@ -162,7 +180,10 @@ __global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
       lds[row][w - 1][2 * k + 1][threadIdx.x] = acc.v[k].im;
     }
   }
-  __syncthreads();
+  // one barrier for the LDS partial terms and alpha
+  double alpha = 0.0;
+  if constexpr (EPI == EPI_CGUPD) alpha = alpha_finish(a, r, row, w == 0, av);
+  else __syncthreads();
   if (w != 0) return;
   double red = 0.0;
   if (active) {
