@@ -831,6 +831,7 @@ void mfq_destroy(mfq_handle* h) {
   release(h->links64);
   release(h->links32);
   release(h->links16);
+  ptc_free(h);
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->ev0) (void)hipEventDestroy(h->ev0);

@@ -39,7 +39,9 @@ struct PtcState {
   DevBuf adam_m, adam_v, grad, part, enorm2;
   OwnedField<float> hid, y, gy, gh;
   OwnedField<double> pr, pe;  // packed training pairs (residuals, errors)
+  DevBuf ops, chi;  // matrix-core weight operands; layer-2 mixings before transport
   int adam_t = 0;
+  int w_version = 0, ops_version = -1;  // ops are rebuilt when the inference weights change
   bool have_weights = false;
 };
 
@@ -86,6 +88,7 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
 // flexible GMRES with the learned (or identity) preconditioner (fgmres.hip)
 int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
 // learned preconditioner (ptc_host.hip)
+void ptc_free(mfq_handle* h);
 int ptc_apply_fields(mfq_handle* h, Field<double> in, Field<double> out, int n, hipStream_t st);
 
 template <typename S, typename SX>

@@ -18,6 +18,17 @@ template <typename SI, typename SO>
 hipError_t ptc_forward(const Geom& g, Links<float> L, Field<SI> in, Field<float> hid, Field<SO> out, const f2* W1,
                        const f2* W2, int n_rhs, float in_scale, float out_scale, hipStream_t st);
 
+// The same forward pass with both mixings on the BF16 matrix instruction
+// (inference): chi (ptc_chi_floats FP32 values) holds the layer-2 mixings
+// chi_p before transport, ops (ptc_ops_bytes) the weight operands that
+// ptc_pack_ops lays out from the inference weights.
+size_t ptc_ops_bytes();
+size_t ptc_chi_floats(const Geom& g, int n_rhs);
+hipError_t ptc_pack_ops(const f2* W1, const f2* W2, void* ops, hipStream_t st);
+template <typename SI, typename SO>
+hipError_t ptc_forward_mx(const Geom& g, Links<float> L, Field<SI> in, float* chi, Field<SO> out, const void* ops,
+                          int n_rhs, hipStream_t st);
+
 // gh[k*8 + c] = sum_p W2[p][c]^+ (T_pbar gy_k): the adjoint of layer 2.
 hipError_t ptc_adjoint2(const Geom& g, Links<float> L, Field<float> gy, Field<float> gh, const f2* W2, int n_pairs,
                         hipStream_t st);

@@ -400,3 +400,286 @@ hipError_t ptc_adam(float* w, const double* grad, float* m, float* v, int n_real
 }
 
 }  // namespace mfq
+
+namespace mfq {
+
+// ------------------------------------------------- matrix-core forward pass
+// Both channel mixings are complex matrix products over (channel, spin) that
+// leave colour alone, so for each colour they are real matrix products over
+// sites once a complex weight w = wr + i wi is written as the 2x2 real block
+// [[wr, -wi], [wi, wr]] acting on (re, im).  They run on the 16x16x32 BF16
+// matrix instruction in transposed form: rows are output components, the 16
+// columns are 16 sites of one parity and one right-hand side, so each lane's
+// results belong to one site and stores coalesce across lanes.
+//
+//   layer 1:  K = 9 paths x 4 spins x (re, im) = 72, padded to 96 (3 steps),
+//             M = 8 channels x 4 spins x (re, im) = 64 (4 tiles);
+//   layer 2:  chi_p = sum_c W2[p][c] h_c is formed at the site that holds h
+//             (the mixing acts on spin, the transport on colour, so they
+//             commute): K = 64 hidden components taken straight from layer
+//             1's accumulators (2 steps), M = 9 paths x 4 spins x (re, im) =
+//             72, padded to 80 (5 tiles).
+// The chi_p go to memory (FP32) and a gather kernel forms
+// out(n) = chi_0(n) + sum_{p>0} (T_p chi_p)(n); the hidden field never leaves
+// registers.
+//
+// Weights are BF16 values (the inference copy) and so exact as BF16
+// operands.  Each FP32 activation x is split as hi = bf16(x),
+// lo = bf16(x - hi), |x - hi - lo| <= 2^-18 |x|, and both halves go through
+// the matrix unit with FP32 accumulation, so the products are those of FP32
+// activations to that relative accuracy.
+//
+// Operand layouts of the instruction (lane l, group g = l / 16, element i of
+// the 8-vector): A: row l % 16, k = 8 g + i;  B: column l % 16, k = 8 g + i;
+// result element e: column l % 16, row 4 g + e.
+//
+// Layer 1's k order lets the four lane groups of a site transport the same
+// paths: in step j, group g holds k = 32 j + 8 g + 2 q + ri for path
+// p = 4 j + q and spin g, so each lane transports one spin of four paths.
+// Layer 2's k order is the order in which layer 1's result elements sit in
+// the lanes: step j, group g, element i is hidden row
+// 16 (2 j + i / 4) + 4 g + (i % 4).
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int MX_L1_TILES = 4, MX_L1_STEPS = 3, MX_L2_TILES = 5, MX_L2_STEPS = 2;
+constexpr int MX_L1_OPS = MX_L1_TILES * MX_L1_STEPS;
+constexpr int MX_OPS = (MX_L1_OPS + MX_L2_TILES * MX_L2_STEPS) * 64;  // 16-byte operands, lane-major
+constexpr int MX_CHI = PTC_PATHS * 2 * 24;  // floats per (rhs, site pair) of chi: [p][parity][24]
+
+// entry of the real 2x2 block of w at (output re/im ro, input re/im ri)
+__device__ __forceinline__ float re_block(f2 w, int ro, int ri) { return ro == ri ? w.x : (ro == 0 ? -w.y : w.y); }
+
+__global__ void ptc_pack_ops_kernel(const f2* W1, const f2* W2, f4* ops_out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= MX_OPS) return;
+  const int l = idx % 64, o = idx / 64, row = l % 16, grp = l / 16;
+  bf16x8 v;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    float x = 0.f;
+    if (o < MX_L1_OPS) {
+      const int t = o / MX_L1_STEPS, j = o % MX_L1_STEPS;
+      const int n = 16 * t + row;  // hidden component: channel n/8, spin (n%8)/2, re/im n%2
+      const int p = 4 * j + i / 2, si = grp, ri = i % 2;
+      if (p < PTC_PATHS) x = re_block(W1[(p * PTC_HIDDEN + n / 8) * 16 + ((n % 8) / 2) * 4 + si], n % 2, ri);
+    } else {
+      const int o2 = o - MX_L1_OPS;
+      const int t = o2 / MX_L2_STEPS, j = o2 % MX_L2_STEPS;
+      const int m = 16 * t + row;                                // chi component: path m/8, spin (m%8)/2, re/im m%2
+      const int n = 16 * (2 * j + i / 4) + 4 * grp + (i % 4);  // hidden component fed at this k
+      if (m < PTC_PATHS * 8)
+        x = re_block(W2[((m / 8) * PTC_HIDDEN + n / 8) * 16 + ((m % 8) / 2) * 4 + (n % 8) / 2], m % 2, n % 2);
+    }
+    v[i] = (__bf16)x;
+  }
+  __builtin_memcpy(&ops_out[idx], &v, sizeof(v));
+}
+
+hipError_t ptc_pack_ops(const f2* W1, const f2* W2, void* ops, hipStream_t st) {
+  hipLaunchKernelGGL(ptc_pack_ops_kernel, dim3((MX_OPS + 255) / 256), dim3(256), 0, st, W1, W2, (f4*)ops);
+  return hipGetLastError();
+}
+
+size_t ptc_ops_bytes() { return (size_t)MX_OPS * 16; }
+size_t ptc_chi_floats(const Geom& g, int n_rhs) { return (size_t)n_rhs * MX_CHI * g.vh; }
+
+// spin sp of a spinor: v[a]
+__device__ __forceinline__ void load_spin(const Field<double>& f, int vr, int par, int s, int sp, cpx<float> v[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const d2 q = f.data[f.cidx(vr, par, 3 * sp + a, s)];
+    v[a] = {(float)q.x, (float)q.y};
+  }
+}
+
+// (T_P psi)(s) restricted to spin sp; zero across an SF boundary and for
+// lanes past the end of the half lattice.
+template <int P, typename SI>
+__device__ __forceinline__ void spin_transport(const Geom& g, const Links<float>& L, const Field<SI>& f, int vr, int s,
+                                               int par, const Coords& c, int sp, bool valid, cpx<float> y[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) y[k] = {0.f, 0.f};
+  if constexpr (P >= PTC_PATHS) {
+    return;
+  } else if constexpr (P == 0) {
+    if (valid) load_spin(f, vr, par, s, sp, y);
+  } else {
+    constexpr int mu = P <= 4 ? P - 1 : P - 5;
+    constexpr bool fwd = P <= 4;
+    const PathHop ph = path_hop(g, c, s, par, mu, fwd);
+    if (!valid || !ph.ok) return;
+    cpx<float> x[3], u[9];
+    load_spin(f, vr, 1 - par, ph.site, sp, x);
+    load_link(L, ph.link_par, mu, ph.link_site, u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<float> acc = {0.f, 0.f};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc = acc + (fwd ? cmul(u[3 * a + b], x[b]) : cjmul(u[3 * b + a], x[b]));
+      y[a] = ph.sgn * acc;
+    }
+  }
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+#define MX_MFMA(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_bf16((a), (b), (c), 0, 0, 0)
+#define MX_SCHED_FENCE __builtin_amdgcn_sched_barrier(0);
+
+// One layer-1 K step: paths 4J .. 4J+3, spin g, 4 tiles, 3 colours.
+template <int J, typename SI>
+__device__ __forceinline__ void mx_l1_step(const Geom& g, const Links<float>& L, const Field<SI>& in, int r, int s,
+                                           int par, const Coords& c, int grp, bool valid,
+                                           const bf16x8* wops, int lane, floatx4 (&acc)[3][MX_L1_TILES]) {
+  cpx<float> y[4][3];
+  spin_transport<4 * J + 0>(g, L, in, r, s, par, c, grp, valid, y[0]);
+  spin_transport<4 * J + 1>(g, L, in, r, s, par, c, grp, valid, y[1]);
+  spin_transport<4 * J + 2>(g, L, in, r, s, par, c, grp, valid, y[2]);
+  spin_transport<4 * J + 3>(g, L, in, r, s, par, c, grp, valid, y[3]);
+  bf16x8 bh[3], bl[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __bf16 hi, lo;
+      split_bf16(y[q][a].re, hi, lo);
+      bh[a][2 * q] = hi;
+      bl[a][2 * q] = lo;
+      split_bf16(y[q][a].im, hi, lo);
+      bh[a][2 * q + 1] = hi;
+      bl[a][2 * q + 1] = lo;
+    }
+#pragma unroll
+  for (int t = 0; t < MX_L1_TILES; ++t) {
+    const bf16x8 w = wops[(t * MX_L1_STEPS + J) * 64 + lane];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a][t] = MX_MFMA(w, bh[a], acc[a][t]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a][t] = MX_MFMA(w, bl[a], acc[a][t]);
+  }
+}
+
+// One wavefront per 16 sites of one parity and one right-hand side (a tile);
+// waves loop over tiles.  The operands of both weight matrices are staged in
+// LDS once per workgroup.  Scheduling fences between the K steps keep the
+// compiler from hoisting every step's neighbour loads to the top, which
+// would take the register count past two waves per SIMD.
+template <typename SI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ptc_mx_kernel(Geom g, Links<float> L, Field<SI> in, float* chi, const f4* ops,
+                                                     int n_tiles) {
+  __shared__ bf16x8 wops[MX_OPS];
+  for (int i = threadIdx.x; i < MX_OPS; i += blockDim.x) __builtin_memcpy(&wops[i], &ops[i], 16);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, grp = lane >> 4;
+  const int tpp = (g.vh + 15) / 16;  // tiles per parity
+  for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * 4) {
+    const int r = tile / (2 * tpp);
+    const int par = (tile / tpp) & 1;
+    const int s0 = (tile % tpp) * 16 + (lane & 15);
+    const bool valid = s0 < g.vh;
+    const int s = valid ? s0 : 0;
+    const Coords c = site_coords(g, s, par);
+    floatx4 acc[3][MX_L1_TILES];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int t = 0; t < MX_L1_TILES; ++t) acc[a][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    mx_l1_step<0>(g, L, in, r, s, par, c, grp, valid, wops, lane, acc);
+    MX_SCHED_FENCE
+    mx_l1_step<1>(g, L, in, r, s, par, c, grp, valid, wops, lane, acc);
+    MX_SCHED_FENCE
+    mx_l1_step<2>(g, L, in, r, s, par, c, grp, valid, wops, lane, acc);
+    MX_SCHED_FENCE
+    float* base = chi + ((long)r * MX_CHI + par * 24) * g.vh + s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      bf16x8 bh[MX_L2_STEPS], bl[MX_L2_STEPS];
+#pragma unroll
+      for (int j = 0; j < MX_L2_STEPS; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __bf16 hi, lo;
+          split_bf16(acc[a][2 * j + i / 4][i % 4], hi, lo);
+          bh[j][i] = hi;
+          bl[j][i] = lo;
+        }
+      floatx4 o[MX_L2_TILES];
+#pragma unroll
+      for (int t = 0; t < MX_L2_TILES; ++t) o[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < MX_L2_STEPS; ++j)
+#pragma unroll
+        for (int t = 0; t < MX_L2_TILES; ++t) {
+          const bf16x8 w = wops[(MX_L1_OPS + t * MX_L2_STEPS + j) * 64 + lane];
+          o[t] = MX_MFMA(w, bh[j], o[t]);
+          o[t] = MX_MFMA(w, bl[j], o[t]);
+        }
+      if (valid) {
+        // row 16 t + 4 g + e = (path 2 t + g / 2, spin 2 (g % 2) + e / 2, re/im e % 2)
+#pragma unroll
+        for (int t = 0; t < MX_L2_TILES; ++t) {
+          const int p = 2 * t + grp / 2;
+          if (p < PTC_PATHS) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int so = 2 * (grp % 2) + e / 2;
+              base[((long)p * 48 + (3 * so + a) * 2 + (e % 2)) * g.vh] = o[t][e];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// out(n) = chi_0(n) + sum_{p>0} (T_p chi_p)(n); chi is [rhs][p][parity][24][vh].
+template <typename SO>
+__global__ __launch_bounds__(256) void ptc_gather_kernel(Geom g, Links<float> L, const float* chi, Field<SO> out,
+                                                         int n_rhs) {
+  PTC_LANE
+  const float* cr = chi + (long)r * MX_CHI * g.vh;
+  Spinor<float> acc;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc.v[k] = {cr[(par * 24 + 2 * k) * (long)g.vh + s], cr[(par * 24 + 2 * k + 1) * (long)g.vh + s]};
+#pragma unroll
+  for (int p = 1; p < PTC_PATHS; ++p) {
+    const int mu = p <= 4 ? p - 1 : p - 5;
+    const bool fwd = p <= 4;
+    const PathHop ph = path_hop(g, c, s, par, mu, fwd);
+    if (!ph.ok) continue;
+    const float* cp = cr + ((long)p * 48 + (1 - par) * 24) * g.vh + ph.site;
+    Spinor<float> x, t;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x.v[k] = {cp[(2 * k) * (long)g.vh], cp[(2 * k + 1) * (long)g.vh]};
+    cpx<float> u[9];
+    load_link(L, ph.link_par, mu, ph.link_site, u);
+    colour_mul(u, !fwd, ph.sgn, x, t);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc.v[k] = acc.v[k] + t.v[k];
+  }
+  store_spinor(out, r, par, s, acc);
+}
+
+template <typename SI, typename SO>
+hipError_t ptc_forward_mx(const Geom& g, Links<float> L, Field<SI> in, float* chi, Field<SO> out, const void* ops,
+                          int n_rhs, hipStream_t st) {
+  const int n_tiles = n_rhs * 2 * ((g.vh + 15) / 16);
+  int blocks = (n_tiles + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((ptc_mx_kernel<SI>), dim3(blocks), dim3(256), 0, st, g, L, in, chi, (const f4*)ops, n_tiles);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((ptc_gather_kernel<SO>), dim3((2 * g.vh + 255) / 256, n_rhs), dim3(256), 0, st, g, L, chi, out,
+                     n_rhs);
+  return hipGetLastError();
+}
+
+template hipError_t ptc_forward_mx<double, double>(const Geom&, Links<float>, Field<double>, float*, Field<double>,
+                                                   const void*, int, hipStream_t);
+
+}  // namespace mfq
