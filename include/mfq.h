@@ -238,7 +238,7 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
 
 /* Launch-shape autotuning of the inner solver's hopping kernel (on by
  * default).  The first solve (or mfq_time_hop) for a given (n_rhs, precision)
- * times candidate (sites per workgroup, RHS per workgroup, XCD remap) shapes
+ * times candidate (sites per workgroup, RHS per workgroup, tile order) shapes
  * with HIP events and keeps the fastest; MFQ_AUTOTUNE_CACHE, if set, names a
  * text file where choices are stored and looked up; if it is not set, the
  * table tune_gfx950.txt next to the library (shapes tuned on MI355X for the
@@ -247,7 +247,9 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
 int mfq_set_autotune(mfq_handle* h, int on);
 
 /* The shape the inner solver uses for (precision, n_rhs): shape5 (host, 5
- * ints) receives {sites per workgroup, RHS per workgroup, XCD remap flag,
+ * ints) receives {sites per workgroup, RHS per workgroup, tile order flags
+ * (bit 0: each XCD walks a contiguous chunk of tiles; bit 1: tiles walked
+ * (z, t) plane by plane over blocks of consecutive z, t before z),
  * time-sweep length (0: one site per thread; else each thread walks that many
  * time slices of one spatial site, sites per workgroup then counting spatial
  * sites), direction split (0, or 2 / 4 wavefronts sharing the 4 directions of

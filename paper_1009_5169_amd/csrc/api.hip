@@ -60,9 +60,9 @@ void drop_graphs(mfq_handle* h) {
   h->graphs.clear();
 }
 
-Links<double> links_d(mfq_handle* h) { return Links<double>{(const d2*)h->links64.ptr, h->g.vh, 0}; }
-Links<float> links_f(mfq_handle* h) { return Links<float>{(const f2*)h->links32.ptr, h->g.vh, 1}; }
-Links<_Float16> links_h(mfq_handle* h) { return Links<_Float16>{(const h2*)h->links16.ptr, h->g.vh, 1}; }
+Links<double> links_d(mfq_handle* h) { return Links<double>{(const d2*)h->links64.ptr, h->g.vs, 0}; }
+Links<float> links_f(mfq_handle* h) { return Links<float>{(const f2*)h->links32.ptr, h->g.vs, 1}; }
+Links<_Float16> links_h(mfq_handle* h) { return Links<_Float16>{(const h2*)h->links16.ptr, h->g.vs, 1}; }
 
 int need_su3(mfq_handle* h, int prec, int precond) {
   if ((prec != MFQ_PREC_FP64 || precond == MFQ_PC_PTC) && !h->links_su3)
@@ -144,13 +144,13 @@ int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field
     case MFQ_OP_HOP_OE: {
       const int par = op == MFQ_OP_HOP_EO ? 0 : 1;
       // zero the other parity of the output, then the one hopping launch
-      const size_t per_par = (size_t)Store<S>::NC * h->g.vh;
+      const size_t per_par = (size_t)Store<S>::NC * h->g.vs;
       for (int r = 0; r < n_rhs; ++r)
         HIPCHK(hipMemsetAsync(out.data + ((size_t)r * 2 + (1 - par)) * per_par, 0,
                               per_par * sizeof(typename Store<S>::chunk), st));
       if (sizeof(S) == 2)
         for (int r = 0; r < n_rhs; ++r)
-          HIPCHK(hipMemsetAsync(out.norm + ((size_t)r * 2 + (1 - par)) * h->g.vh, 0, h->g.vh * sizeof(float), st));
+          HIPCHK(hipMemsetAsync(out.norm + ((size_t)r * 2 + (1 - par)) * h->g.vs, 0, h->g.vs * sizeof(float), st));
       HIPCHK(run(EPI_HOP, in, out, par, 0, 1.0));
       return MFQ_OK;
     }
@@ -219,7 +219,7 @@ bool tune_cache_lookup(mfq_handle* h, int n, int prec, Shape* out) {
                      nr * (ds - 1) * 24 * 64 * (prec == 8 ? 8 : 4) <= 65536))) {
       out->sb = sb;
       out->nr = nr;
-      out->xcd = xcd ? 1 : 0;
+      out->xcd = xcd & 3;
       out->tc = tc;
       out->ds = ds;
       found = true;
@@ -250,7 +250,8 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
       if (nr > n || sb * nr > 512 || (k > 0 && nr == nrs[k - 1])) continue;
       for (int tc = 0; tc <= 4; tc += 4) {  // the time sweep measured slower so far: one candidate
         if (tc >= 2 * h->g.td) continue;  // one chunk already covers the time extent
-        for (int xcd = 0; xcd < 2; ++xcd) {
+        for (int xcd = 0; xcd < 4; ++xcd) {
+          if ((xcd & 2) && tc) continue;  // the time sweep has its own order
           for (int ds = 0; ds <= 4; ds += 2) {
             // split: 64 sites x nr RHS, ds * nr waves, partial hopping terms in LDS
             if (ds && (sb != 64 || ds * nr > 8 || tc || nr * (ds - 1) * 24 * 64 * (prec == 8 ? 8 : 4) > 65536))
@@ -319,7 +320,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   HIPCHK(launch_finish(FIN_INIT, &p0, 1, n, sc, nullptr, tol2, delta2, st));
   HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, field_chunks<double>(g, n) * sizeof(d2), st));
   HIPCHK(hipMemsetAsync(in.x.data, 0, field_chunks<SX>(g, n) * sizeof(typename Store<SX>::chunk), st));
-  if (sizeof(SX) == 2) HIPCHK(hipMemsetAsync(in.x.norm, 0, (size_t)n * 2 * g.vh * sizeof(float), st));
+  if (sizeof(SX) == 2) HIPCHK(hipMemsetAsync(in.x.norm, 0, (size_t)n * 2 * g.vs * sizeof(float), st));
   HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, sh, st));
 
   HopArgs<S, SX> a = hop_args<S, SX>(h, in.L, n);
@@ -600,8 +601,13 @@ int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mf
   g.t0 = lat->bc == MFQ_BC_SF ? 1 : 0;
   g.lxh = g.lx / 2;
   g.vh = g.lxh * g.ly * g.lz * g.td;
+  {
+    int gr = (g.vh + 15) / 16;  // 256-byte granules of a 16-byte-per-site array
+    if (gr % 2 == 0) gr += 1;
+    g.vs = 16 * gr;
+  }
   h->n_slices = lat->bc == MFQ_BC_SF ? lat->dims[3] + 1 : lat->dims[3];
-  const size_t nl = (size_t)2 * 4 * 9 * g.vh;
+  const size_t nl = (size_t)2 * 4 * 9 * g.vs;
   hipError_t e;
   if ((e = ensure(h->links64, nl * sizeof(d2))) != hipSuccess ||
       (e = ensure(h->links32, nl * sizeof(f2))) != hipSuccess ||

@@ -15,6 +15,9 @@
 //   link array          FP64 [parity][mu][9][site] (double2); FP32 / FP16
 //                       [parity][mu][3][site] chunks of the first two rows
 //
+// The [site] dimension of every array has the padded length Geom::vs >= vh
+// (the padding is never read or written).
+//
 // A "site" is a half-lattice index s = xh + (Lx/2)(y + Ly(z + Lz t)) over the
 // dynamical time slices t = 0..Td-1 (x0 = t + 1 under Schroedinger-functional
 // boundaries, x0 = t otherwise); its x coordinate is 2 xh + ((x0+y+z+p) & 1).
@@ -71,6 +74,12 @@ struct Geom {
   int vh;              // half volume of the dynamical lattice
   int t0;              // x0 of the first dynamical slice (1 for SF, else 0)
   int bc;
+  // Storage stride (in sites) of every SoA component array: vh rounded up to
+  // 16 times an odd number, so the arrays of one site start an odd number of
+  // 256-byte granules apart.  With a power-of-two stride (vh = 2^20 at
+  // 32^3 x 64) all components of a site fall in one L2 channel and set and
+  // evict each other.
+  int vs;
 };
 
 struct Coords {

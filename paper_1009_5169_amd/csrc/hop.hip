@@ -27,6 +27,19 @@ __device__ __forceinline__ int tile_index(int remap) {
   return xcd * q + (xcd < rem ? xcd : rem) + (b >> 3);
 }
 
+// First half-lattice site of logical tile k (sb sites per tile).
+template <typename S, typename SX>
+__device__ __forceinline__ int tile_site0(const HopArgs<S, SX>& a, int k, int sb) {
+  if (!a.zb) return k * sb;
+  const int yt = k % a.tpp;
+  int rest = k / a.tpp;
+  const int zi = rest % a.zb;
+  rest /= a.zb;
+  const int t = rest % a.g.td;
+  const int z = (rest / a.g.td) * a.zb + zi;
+  return yt * sb + a.g.lxh * a.g.ly * (z + a.g.lz * t);
+}
+
 // The CG step length for RHS row `row`: from the scalars, or, when the
 // |D p|^2 partials are passed (small lattices), reduced here by the row's
 // leader wavefront in the same fixed order as the finishing kernel.  Split in
@@ -79,9 +92,9 @@ __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
   int s;
   if (par == 2) {
     par = tile & 1;
-    s = (tile >> 1) * blockDim.x + threadIdx.x;
+    s = tile_site0(a, tile >> 1, blockDim.x) + threadIdx.x;
   } else {
-    s = tile * blockDim.x + threadIdx.x;
+    s = tile_site0(a, tile, blockDim.x) + threadIdx.x;
   }
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
   double av = 0.0;
@@ -149,9 +162,9 @@ __global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
   int s;
   if (par == 2) {
     par = tile & 1;
-    s = (tile >> 1) * 64 + threadIdx.x;
+    s = tile_site0(a, tile >> 1, 64) + threadIdx.x;
   } else {
-    s = tile * 64 + threadIdx.x;
+    s = tile_site0(a, tile, 64) + threadIdx.x;
   }
   const int row = threadIdx.y / DS, w = threadIdx.y - row * DS;
   const int r = blockIdx.y * (blockDim.y / DS) + row;
@@ -240,7 +253,17 @@ int max_hop_blocks(const Geom& g) {
 template <typename S, typename SX>
 hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st) {
   HopArgs<S, SX> b = a;
-  b.xcd = sh.xcd;
+  b.xcd = sh.xcd & 1;
+  b.zb = 0;
+  b.tpp = 0;
+  {
+    const int sbe = (sh.ds == 2 || sh.ds == 4) ? 64 : sh.sb;
+    const int plane = a.g.lxh * a.g.ly;  // half sites per (z, t) plane
+    if ((sh.xcd & 2) && (sh.tc == 0 || sh.ds > 1) && plane % sbe == 0) {
+      b.zb = a.g.lz % 4 == 0 ? 4 : (a.g.lz % 2 == 0 ? 2 : 1);
+      b.tpp = plane / sbe;
+    }
+  }
   if (sh.ds == 2 || sh.ds == 4) {
     Shape s64 = sh;
     s64.sb = 64;

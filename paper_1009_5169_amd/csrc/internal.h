@@ -71,7 +71,8 @@ struct Partials {
 struct Shape {
   int sb;   // sites per workgroup (multiple of 64)
   int nr;   // right-hand sides per workgroup
-  int xcd;  // remap workgroups so each XCD walks a contiguous chunk of sites
+  int xcd;  // bit 0: remap workgroups so each XCD walks a contiguous chunk of
+            // tiles; bit 1: z-blocked tile order (see HopArgs::zb)
   int tc;   // both-parity launches: 0, or each thread sweeps tc time slices of
             // one spatial site (sb spatial sites per workgroup)
   int ds;   // 0, or 2 / 4: the 4 directions of a site split over that many
@@ -106,6 +107,12 @@ struct HopArgs {
   int n_rhs, dagger, skip_state;
   int upd_mode;        // >= 0: run only the RHS in_update(sc[r], upd_mode); else use skip_state
   int xcd;             // set by the launcher from the Shape
+  // z-blocked tile order (0: tiles in half-index order).  Tiles are whole
+  // pieces of one (z, t) plane; they are walked plane by plane over zb
+  // consecutive z, then t, then the next block of zb z values, so a spinor's
+  // and a link's t and z neighbours are read a few dozen tiles apart, inside
+  // one XCD's L2, instead of a whole time slice apart.  tpp = tiles per plane.
+  int zb, tpp;
   double coef;         // coefficient of the hopping term
 };
 
@@ -159,7 +166,7 @@ void release(DevBuf& b);
 
 template <typename S>
 size_t field_chunks(const Geom& g, int n_rhs) {
-  return (size_t)n_rhs * 2 * Store<S>::NC * g.vh;
+  return (size_t)n_rhs * 2 * Store<S>::NC * g.vs;
 }
 
 template <typename S>
@@ -168,14 +175,14 @@ struct OwnedField {
   hipError_t alloc(const Geom& g, int n_rhs) {
     hipError_t e = ensure(data, field_chunks<S>(g, n_rhs) * sizeof(typename Store<S>::chunk));
     if (e != hipSuccess) return e;
-    if (sizeof(S) == 2) return ensure(norm, (size_t)n_rhs * 2 * g.vh * sizeof(float));
+    if (sizeof(S) == 2) return ensure(norm, (size_t)n_rhs * 2 * g.vs * sizeof(float));
     return hipSuccess;
   }
   Field<S> view(const Geom& g) const {
     Field<S> f;
     f.data = (typename Store<S>::chunk*)data.ptr;
     f.norm = (float*)norm.ptr;
-    f.vh = g.vh;
+    f.vh = g.vs;
     return f;
   }
   void free_all() {

@@ -127,7 +127,7 @@ __global__ void pack_links_kernel(Geom g, const d2* canon, typename Store<S>::li
         e.y = (S)u[2 * c].im;
         e.z = (S)u[2 * c + 1].re;
         e.w = (S)u[2 * c + 1].im;
-        co[((long)(par * 4 + mu) * 3 + c) * g.vh + s] = e;
+        co[((long)(par * 4 + mu) * 3 + c) * g.vs + s] = e;
       }
       return;
     }
@@ -137,7 +137,7 @@ __global__ void pack_links_kernel(Geom g, const d2* canon, typename Store<S>::li
     typename Store<S>::link_elem e;
     e.x = (S)u[k].re;
     e.y = (S)u[k].im;
-    out[((long)(par * 4 + mu) * 9 + k) * g.vh + s] = e;
+    out[((long)(par * 4 + mu) * 9 + k) * g.vs + s] = e;
   }
 }
 

@@ -483,7 +483,7 @@ hipError_t ptc_pack_ops(const f2* W1, const f2* W2, void* ops, hipStream_t st) {
 }
 
 size_t ptc_ops_bytes() { return (size_t)MX_OPS * 16; }
-size_t ptc_chi_floats(const Geom& g, int n_rhs) { return (size_t)n_rhs * MX_CHI * g.vh; }
+size_t ptc_chi_floats(const Geom& g, int n_rhs) { return (size_t)n_rhs * MX_CHI * g.vs; }
 
 // spin sp of a spinor: v[a]
 __device__ __forceinline__ void load_spin(const Field<double>& f, int vr, int par, int s, int sp, cpx<float> v[3]) {
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
     MX_SCHED_FENCE
     mx_l1_step<2>(g, L, in, r, s, par, c, grp, valid, wops, lane, acc);
     MX_SCHED_FENCE
-    float* base = chi + ((long)r * MX_CHI + par * 24) * g.vh + s;
+    float* base = chi + ((long)r * MX_CHI + par * 24) * g.vs + s;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       bf16x8 bh[MX_L2_STEPS], bl[MX_L2_STEPS];
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const int so = 2 * (grp % 2) + e / 2;
-              base[((long)p * 48 + (3 * so + a) * 2 + (e % 2)) * g.vh] = o[t][e];
+              base[((long)p * 48 + (3 * so + a) * 2 + (e % 2)) * g.vs] = o[t][e];
             }
           }
         }
@@ -637,25 +637,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   }
 }
 
-// out(n) = chi_0(n) + sum_{p>0} (T_p chi_p)(n); chi is [rhs][p][parity][24][vh].
+// out(n) = chi_0(n) + sum_{p>0} (T_p chi_p)(n); chi is [rhs][p][parity][24][vs].
 template <typename SO>
 __global__ __launch_bounds__(256) void ptc_gather_kernel(Geom g, Links<float> L, const float* chi, Field<SO> out,
                                                          int n_rhs) {
   PTC_LANE
-  const float* cr = chi + (long)r * MX_CHI * g.vh;
+  const float* cr = chi + (long)r * MX_CHI * g.vs;
   Spinor<float> acc;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc.v[k] = {cr[(par * 24 + 2 * k) * (long)g.vh + s], cr[(par * 24 + 2 * k + 1) * (long)g.vh + s]};
+  for (int k = 0; k < 12; ++k) acc.v[k] = {cr[(par * 24 + 2 * k) * (long)g.vs + s], cr[(par * 24 + 2 * k + 1) * (long)g.vs + s]};
 #pragma unroll
   for (int p = 1; p < PTC_PATHS; ++p) {
     const int mu = p <= 4 ? p - 1 : p - 5;
     const bool fwd = p <= 4;
     const PathHop ph = path_hop(g, c, s, par, mu, fwd);
     if (!ph.ok) continue;
-    const float* cp = cr + ((long)p * 48 + (1 - par) * 24) * g.vh + ph.site;
+    const float* cp = cr + ((long)p * 48 + (1 - par) * 24) * g.vs + ph.site;
     Spinor<float> x, t;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) x.v[k] = {cp[(2 * k) * (long)g.vh], cp[(2 * k + 1) * (long)g.vh]};
+    for (int k = 0; k < 12; ++k) x.v[k] = {cp[(2 * k) * (long)g.vs], cp[(2 * k + 1) * (long)g.vs]};
     cpx<float> u[9];
     load_link(L, ph.link_par, mu, ph.link_site, u);
     colour_mul(u, !fwd, ph.sgn, x, t);

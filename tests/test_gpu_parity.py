@@ -183,6 +183,40 @@ def test_forced_launch_shapes_match_oracle(tmp_path, monkeypatch, shape, prec):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(64, 1, 2, 0, 0), (64, 3, 3, 0, 0), (64, 1, 2, 0, 4), (64, 2, 3, 0, 2),
+                                   (128, 1, 3, 0, 0)],
+                         ids=lambda s: "sb%d_nr%d_xcd%d_tc%d_ds%d" % s)
+@pytest.mark.parametrize("lattice", [((8, 16, 6, 6), "sf"), ((8, 16, 4, 4), "periodic")],
+                         ids=["sf8x16x6x6", "periodic8x16x4x4"])
+def test_z_blocked_tile_order_matches_oracle(tmp_path, monkeypatch, lattice, shape, prec):
+    """The z-blocked tile order (bit 1 of the order flags) on lattices whose
+    (z, t) planes hold whole 64-site tiles: blocks of 2 z values over 5 SF
+    time slices and of 4 over 4 periodic ones, with and without the XCD
+    remap, plain and direction-split kernels; 128-site tiles do not divide the
+    64-site planes, so that shape keeps the half-index order.  Solutions meet
+    the oracle's residual and error bound."""
+    dims, bc = lattice
+    kappa, n, tol = 0.13, 3, 1e-10
+    key = "gfx950 %d %d %d %d %d %d %d" % (dims + (BC_CODE[bc], n, PREC_BYTES[prec]))
+    cache = tmp_path / "tune.txt"
+    cache.write_text(key + "|%d %d %d %d %d\n" % shape)
+    monkeypatch.setenv("MFQ_AUTOTUNE_CACHE", str(cache))
+    _, lat, d = make(dims, bc, kappa, 0.4, 1110)
+    b = synth.gaussian_spinors(dims, bc, n, 2110)
+    x, stats, rc = lat.solve(to_dev(b), tol=tol, prec=prec, max_iter=5000)
+    assert tuple(lat.hop_shape(prec, n)) == shape
+    assert rc == 0, stats
+    x = to_host(x)
+    for i in range(n):
+        res = np.linalg.norm(b[i:i + 1] - d.DdagD(x[i:i + 1])) / np.linalg.norm(b[i])
+        assert res <= tol * 1.05, (i, res)
+    x_ref, _ = solvers.cg_normal(d, b, 1e-14)
+    c = _cond(d, b)
+    assert rel(x, x_ref) <= c * (tol + 1e-14) + 1e-14, (rel(x, x_ref), c)
+    lat.close()
+
+
 def test_solve_fp64_tight_matches_oracle_to_1e12():
     """On the 4^4 SF case (cond ~ 180) an FP64 solve to 1e-12/cond reproduces
     the oracle's solution to 1e-12."""
