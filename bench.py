@@ -18,6 +18,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +104,9 @@ def main():
                     help="skip the batch, FP16 and learned-preconditioner measurements")
     ap.add_argument("--profile-big", action="store_true",
                     help="with --profile-kernels: also the bandwidth lattice, 1 and 5 RHS")
+    ap.add_argument("--order-ab", action="store_true",
+                    help="with --profile-kernels: on the bandwidth lattice, 1 RHS, time the direction-split "
+                         "kernel in half-index tile order and then in z-blocked order (forced launch shapes)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the roofline kernel (solve shape) and a 1 GiB copy, for counter runs")
     args = ap.parse_args()
@@ -383,12 +387,35 @@ def profile_kernels(args, synth, mfq, torch, dev, np):
     torch.cuda.synchronize()
     out["copy_bytes"] = src.numel() * 8
     del src, dst
-    if args.profile_big:
+    if args.profile_big or args.order_ab:
         dims = tuple(int(v) for v in args.bw_dims.split(","))
         big = bandwidth_lattice(dims, synth, mfq, torch, dev, np)
-        for nr in (1, 5):
-            out[f"big_n{nr}_ms"] = big.time_hop(args.prec, nr, iters=20)
-            out[f"big_n{nr}_shape"] = big.hop_shape(args.prec, nr)
+        if args.profile_big:
+            for nr in (1, 5):
+                out[f"big_n{nr}_ms"] = big.time_hop(args.prec, nr, iters=20)
+                out[f"big_n{nr}_shape"] = big.hop_shape(args.prec, nr)
+        if args.order_ab:
+            # the same kernel and grid twice: half-index order, then z-blocked order
+            # (each XCD walks (z, t) planes, t before the next block of z values);
+            # counter summaries tell the two apart by dispatch order
+            pb = {"fp64": 8, "fp32": 4, "fp16": 2}[args.prec]
+            key = "gfx950 %d %d %d %d 1 1 %d" % (dims + (pb,))
+            with tempfile.TemporaryDirectory() as td:
+                cache = os.path.join(td, "tune.txt")
+                old = os.environ.get("MFQ_AUTOTUNE_CACHE")
+                os.environ["MFQ_AUTOTUNE_CACHE"] = cache
+                try:
+                    for name, shape in (("linear", (64, 1, 1, 0, 4)), ("zblocked", (64, 1, 3, 0, 4))):
+                        with open(cache, "w") as f:
+                            f.write(key + "|%d %d %d %d %d\n" % shape)
+                        big.set_autotune(True)
+                        out[f"order_{name}_ms"] = big.time_hop(args.prec, 1, iters=20)
+                        out[f"order_{name}_shape"] = big.hop_shape(args.prec, 1)
+                finally:
+                    if old is None:
+                        del os.environ["MFQ_AUTOTUNE_CACHE"]
+                    else:
+                        os.environ["MFQ_AUTOTUNE_CACHE"] = old
         big.close()
     print(json.dumps(out))
 
