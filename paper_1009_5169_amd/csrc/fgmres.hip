@@ -56,29 +56,28 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* part_a, d
   __syncthreads();
 }
 
-// <v_l, w> for l < nv, and with `first` also |w|^2 as entry nv: partials
-// part[((r * (nv + 1) + l) * nblk + blk) * 2 + {re, im}].  The second pass
-// runs only for the RHS whose first pass asked for it (the whole workgroup
-// belongs to one RHS, so it returns together).
-__global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> V, size_t vstride, int nv,
-                                                          Field<double> w, int n_rhs, double* part, int first,
-                                                          const GmState* st) {
+// <v_l, w> for l < NV, and with `first` also |w|^2 as entry NV: partials
+// part[((r * (NV + 1) + l) * nblk + blk) * 2 + {re, im}].  All NV dot
+// products accumulate in registers (the basis vectors' loads issue together)
+// and meet in one workgroup reduction.  The second pass runs only for the RHS
+// whose first pass asked for it (the whole workgroup belongs to one RHS, so it
+// returns together).
+template <int NV>
+__global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> V, size_t vstride, Field<double> w,
+                                                          int n_rhs, double* part, int first, const GmState* st) {
   GM_LANE
   if (!first && !st[r].reorth) return;
-  Spinor<double> ww;
-  if (valid) load_spinor(w, r, par, s, ww);
-  const int nblk = gridDim.x;
-  if (first) {
-    double v = 0.0;
-    if (valid)
+  constexpr int NVAL = 2 * NV + 1;
+  double acc[NVAL];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) v += norm2(ww.v[k]);
-    double* base = part + (((long)r * (nv + 1) + nv) * nblk + blockIdx.x) * 2;
-    block_sum2(v, 0.0, base, base + 1);
-  }
-  for (int l = 0; l < nv; ++l) {
-    double re = 0.0, im = 0.0;
-    if (valid) {
+  for (int i = 0; i < NVAL; ++i) acc[i] = 0.0;
+  if (valid) {
+    Spinor<double> ww;
+    load_spinor(w, r, par, s, ww);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[2 * NV] += norm2(ww.v[k]);
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
       Field<double> vl = V;
       vl.data += l * vstride;
       Spinor<double> vv;
@@ -86,12 +85,30 @@ __global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> 
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
         const cpx<double> d = cjmul(vv.v[k], ww.v[k]);
-        re += d.re;
-        im += d.im;
+        acc[2 * l] += d.re;
+        acc[2 * l + 1] += d.im;
       }
     }
-    double* base = part + (((long)r * (nv + 1) + l) * nblk + blockIdx.x) * 2;
-    block_sum2(re, im, base, base + 1);
+  }
+  __shared__ double ws[4][NVAL];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NVAL; ++i) {
+    const double v = wave_sum(acc[i]);
+    if (lane == 0) ws[wv][i] = v;
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < 2 * NV || (first && i == 2 * NV)) {
+    const double v = ((ws[0][i] + ws[1][i]) + ws[2][i]) + ws[3][i];
+    const int l = i / 2;  // i = 2 NV gives l = NV, the |w|^2 entry
+    double* base = part + (((long)r * (NV + 1) + l) * gridDim.x + blockIdx.x) * 2;
+    if (i < 2 * NV) {
+      base[i % 2] = v;
+    } else {
+      base[0] = v;
+      base[1] = 0.0;
+    }
   }
 }
 
@@ -131,25 +148,28 @@ __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int 
   }
 }
 
-// w -= sum_l c_l v_l.  After the first pass, workgroup 0 of each RHS decides
-// whether the second pass is needed: the projected norm |w'|^2 = |w|^2 -
-// sum |c_l|^2 below half of |w|^2 (|w'| < 0.7 |w|, Kahan's criterion) means
-// cancellation has eaten the orthogonality and the pass is repeated.  No
-// other workgroup of this launch reads the flag.
-__global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double> V, size_t vstride, int nv,
-                                                           Field<double> w, int n_rhs, GmState* st, int first) {
+// w -= sum_l c_l v_l (l < NV, unrolled so that the loads issue together).
+// After the first pass, workgroup 0 of each RHS decides whether the second
+// pass is needed: the projected norm |w'|^2 = |w|^2 - sum |c_l|^2 below half
+// of |w|^2 (|w'| < 0.7 |w|, Kahan's criterion) means cancellation has eaten
+// the orthogonality and the pass is repeated.  No other workgroup of this
+// launch reads the flag.
+template <int NV>
+__global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double> V, size_t vstride, Field<double> w,
+                                                           int n_rhs, GmState* st, int first) {
   GM_LANE
   if (!first && !st[r].reorth) return;
   if (first && blockIdx.x == 0 && threadIdx.x == 0) {
     double c2 = 0.0;
-    for (int l = 0; l < nv; ++l) c2 += st[r].cr[l] * st[r].cr[l] + st[r].ci[l] * st[r].ci[l];
+    for (int l = 0; l < NV; ++l) c2 += st[r].cr[l] * st[r].cr[l] + st[r].ci[l] * st[r].ci[l];
     const double w2 = st[r].w2;
     st[r].reorth = !(w2 - c2 > 0.49 * w2);
   }
   if (!valid) return;
   Spinor<double> ww;
   load_spinor(w, r, par, s, ww);
-  for (int l = 0; l < nv; ++l) {
+#pragma unroll
+  for (int l = 0; l < NV; ++l) {
     const cpx<double> c = {st[r].cr[l], st[r].ci[l]};
     Field<double> vl = V;
     vl.data += l * vstride;
@@ -159,6 +179,39 @@ __global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double>
     for (int k = 0; k < 12; ++k) ww.v[k] = ww.v[k] - cmul(c, vv.v[k]);
   }
   store_spinor(w, r, par, s, ww);
+}
+
+#define GM_NV_CASES(X)                                                                                              \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) \
+  X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+static_assert(GM_MAXM == 32, "one multidot / multiaxpy instance per basis size 1..GM_MAXM");
+
+hipError_t launch_multidot(int nv, dim3 grid, dim3 blk, hipStream_t st, const Geom& g, Field<double> V,
+                           size_t vstride, Field<double> w, int n, double* part, int first, const GmState* S) {
+  switch (nv) {
+#define GM_DOT(N)                                                                                                \
+  case N:                                                                                                        \
+    hipLaunchKernelGGL((gm_multidot_kernel<N>), grid, blk, 0, st, g, V, vstride, w, n, part, first, S);          \
+    break;
+    GM_NV_CASES(GM_DOT)
+#undef GM_DOT
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy(int nv, dim3 grid, dim3 blk, hipStream_t st, const Geom& g, Field<double> V,
+                            size_t vstride, Field<double> w, int n, GmState* S, int first) {
+  switch (nv) {
+#define GM_AXPY(N)                                                                                               \
+  case N:                                                                                                        \
+    hipLaunchKernelGGL((gm_multiaxpy_kernel<N>), grid, blk, 0, st, g, V, vstride, w, n, S, first);               \
+    break;
+    GM_NV_CASES(GM_AXPY)
+#undef GM_AXPY
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void gm_norm_kernel(Geom g, Field<double> w, int n_rhs, double* part) {
@@ -420,10 +473,10 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
       // the other RHS)
       for (int pass = 0; pass < 2; ++pass) {
         const int first = pass == 0 ? 1 : 0;
-        hipLaunchKernelGGL(gm_multidot_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, part, first, S);
+        HIPCHK(launch_multidot(j + 1, grid, blk, st, g, V, fch, W, n, part, first, S));
         hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 2) + 3) / 4), dim3(256), 0, st, part, nblk, j + 1,
                            n, S, j, first);
-        hipLaunchKernelGGL(gm_multiaxpy_kernel, grid, blk, 0, st, g, V, fch, j + 1, W, n, S, first);
+        HIPCHK(launch_multiaxpy(j + 1, grid, blk, st, g, V, fch, W, n, S, first));
       }
       if ((rc = norm_finish(W, j, 0))) return cleanup(), rc;
       hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, W, vj(V, j + 1), n, S);
