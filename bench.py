@@ -163,8 +163,8 @@ def main():
                 "algorithmic_bytes_per_launch": int(per_launch)}
 
     # solve-only times on the same GPU: this precision and plain FP64 CG
-    def solve_ms(prec, reps=5):
-        pr = mfq.make_params(tol=1e-10, prec=prec, max_iter=20000)
+    def solve_ms(prec, reps=5, precond="none"):
+        pr = mfq.make_params(tol=1e-10, prec=prec, max_iter=20000, precond=precond)
         lat.solve(phi, params=pr)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -176,6 +176,7 @@ def main():
     s_ms, x_this, st_this = solve_ms(args.prec)
     s64_ms, x64, st64 = solve_ms("fp64")
     s16_ms, x16, st16 = solve_ms("fp16")
+    sb_ms, xb, stb = solve_ms("fp64", precond="blockcg")  # one Krylov space for all RHS
     x64h = x64.cpu().numpy()
     err = lambda a: float(np.linalg.norm(a.cpu().numpy() - x64h) / np.linalg.norm(x64h))
 
@@ -189,11 +190,12 @@ def main():
                    "step": "blocked force: batched CG on DdagD + g5 map + force + action",
                    "inner_precision": args.prec},
         "roofline": roofline,
-        "solve_ms": {args.prec: round(s_ms, 4), "fp64": round(s64_ms, 4), "fp16": round(s16_ms, 4)},
+        "solve_ms": {args.prec: round(s_ms, 4), "fp64": round(s64_ms, 4), "fp16": round(s16_ms, 4),
+                     "block_cg_fp64": round(sb_ms, 4)},
         "solve_speedup_vs_fp64_cg": round(s64_ms / s_ms, 3),
         "iters": {args.prec: [s["iters"] for s in st_this], "fp64": [s["iters"] for s in st64],
-                  "fp16": [s["iters"] for s in st16]},
-        "solution_rel_err_vs_fp64_path": {args.prec: err(x_this), "fp16": err(x16)},
+                  "fp16": [s["iters"] for s in st16], "block_cg_fp64": [s["iters"] for s in stb]},
+        "solution_rel_err_vs_fp64_path": {args.prec: err(x_this), "fp16": err(x16), "block_cg_fp64": err(xb)},
         "true_rel_resid_max": max(s["true_rel_resid"] for s in st_this),
     }
 
@@ -256,7 +258,8 @@ def _timed(fn, reps=3):
 
 def bench_fp16(synth, mfq, torch, dev, np):
     """16^3x16 SF, eps = 0.5, kappa = 0.135, 5 RHS: FP16 storage (per-site norm)
-    with FP64 defect correction against FP32 and plain FP64 CG, to 1e-10."""
+    with FP64 defect correction against FP32 and plain FP64 CG, and FP64 block
+    CG (one Krylov space for the 5 RHS), all to 1e-10."""
     p = synth.CONFIG_2
     print(f"[bench] row fp16 {p.name}", file=sys.stderr, flush=True)
     lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
@@ -271,6 +274,14 @@ def bench_fp16(synth, mfq, torch, dev, np):
                      "true_rel_resid_max": max(s["true_rel_resid"] for s in st)}
     for prec in ("fp32", "fp16"):
         res[prec]["rel_err_vs_fp64_path"] = float(np.linalg.norm(xs[prec] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+    # block CG: the 5 RHS share one Krylov space (FP64)
+    pr = mfq.make_params(tol=1e-10, prec="fp64", precond="blockcg", max_iter=50000)
+    ms, (x, st, rc) = _timed(lambda: lat.solve(b, params=pr))
+    res["block_cg_fp64"] = {"ms": round(ms, 3), "rc": rc, "iters": [s["iters"] for s in st],
+                            "true_rel_resid_max": max(s["true_rel_resid"] for s in st),
+                            "rel_err_vs_fp64_path": float(np.linalg.norm(x.cpu().numpy() - xs["fp64"])
+                                                          / np.linalg.norm(xs["fp64"])),
+                            "iteration_ratio_vs_fp64_cg": round(st[0]["iters"] / max(res["fp64"]["iters"]), 3)}
     lat.close()
     return res
 

@@ -98,8 +98,14 @@ typedef enum {
  * the learned parallel-transport network, with CG as the fallback when a
  * cycle stagnates or breaks down (status MFQ_FELL_BACK); IDENTITY is the same
  * GMRES without preconditioner (the reference the network is measured
- * against). */
-typedef enum { MFQ_PC_NONE = 0, MFQ_PC_PTC = 1, MFQ_PC_IDENTITY = 2 } mfq_pc;
+ * against).  BLOCKCG is block conjugate gradients on D^+D: the n_rhs (<= 8)
+ * right-hand sides share one Krylov space (the CG counterpart of the block
+ * Krylov solvers of Sec. 3.1); FP64 only (prec must be MFQ_PREC_FP64, else
+ * MFQ_ERR_ARG), every iteration is one D^+D on all RHS plus n x n complex
+ * Gram matrices and solves in FP64; it restarts from the FP64 true residual
+ * if the recursive residual drifted, and hands the remaining residual to
+ * batched CG (status MFQ_FELL_BACK) if an n x n solve breaks down. */
+typedef enum { MFQ_PC_NONE = 0, MFQ_PC_PTC = 1, MFQ_PC_IDENTITY = 2, MFQ_PC_BLOCKCG = 3 } mfq_pc;
 
 typedef struct {
   int dims[4]; /* Lx, Ly, Lz, T: even, >= 2 (T >= 4 for SF)                  */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmfq.so")
 BC = {"sf": 0, "periodic": 1, "antiperiodic": 2}
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 OPS = {"hop_eo": 0, "hop_oe": 1, "D": 2, "Ddag": 3, "DdagD": 4, "hop": 5, "hop_dag": 6}
-PRECOND = {"none": 0, "ptc": 1, "identity": 2}
+PRECOND = {"none": 0, "ptc": 1, "identity": 2, "blockcg": 3}
 
 MFQ_OK, MFQ_NOT_CONVERGED, MFQ_FELL_BACK = 0, 1, 2
 

@@ -509,7 +509,7 @@ int check_params(const mfq_solve_params* P) {
   if (!(P->tol > 0.0) || P->tol >= 1.0) return fail(MFQ_ERR_ARG, "tol must be in (0, 1)");
   if (P->max_iter < 1) return fail(MFQ_ERR_ARG, "max_iter must be >= 1");
   if (P->prec < MFQ_PREC_FP64 || P->prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
-  if (P->precond < MFQ_PC_NONE || P->precond > MFQ_PC_IDENTITY) return fail(MFQ_ERR_ARG, "unknown preconditioner");
+  if (P->precond < MFQ_PC_NONE || P->precond > MFQ_PC_BLOCKCG) return fail(MFQ_ERR_ARG, "unknown solver selection");
   if (P->restart > 32) return fail(MFQ_ERR_ARG, "restart must be <= 32");
   return MFQ_OK;
 }
@@ -518,6 +518,7 @@ int check_params(const mfq_solve_params* P) {
 int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
   if (int rc = need_su3(h, P->prec, P->precond)) return rc;
   if (P->precond == MFQ_PC_PTC || P->precond == MFQ_PC_IDENTITY) return run_fgmres(h, n, P, st, stats);
+  if (P->precond == MFQ_PC_BLOCKCG) return run_block_cg(h, n, P, st, stats);
   Workspace& w = h->ws;
   const Geom& g = h->g;
   const double delta = P->reliable_delta > 0.0 ? P->reliable_delta : 0.1;
@@ -548,6 +549,14 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       return run_cg<_Float16, float>(h, n, P, in, delta, st, stats);
     }
   }
+}
+
+int fp64_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out) {
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  HIPCHK(w.pd.alloc(g, n));
+  HIPCHK(w.td.alloc(g, n));
+  return tuned_shape<double, double>(h, n, 8, links_d(h), w.pd.view(g), w.td.view(g), st, out);
 }
 
 int ensure_fp64_fields(mfq_handle* h, int n) {

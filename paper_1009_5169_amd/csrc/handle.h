@@ -87,6 +87,9 @@ int pack_checked(mfq_handle* h, const double* canon, int n_rhs, int gamma5, hipS
 int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
 // flexible GMRES with the learned (or identity) preconditioner (fgmres.hip)
 int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
+int run_block_cg(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
+// the tuned launch shape of the FP64 hopping kernel for n RHS
+int fp64_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out);
 // learned preconditioner (ptc_host.hip)
 void ptc_free(mfq_handle* h);
 int ptc_apply_fields(mfq_handle* h, Field<double> in, Field<double> out, int n, hipStream_t st);
