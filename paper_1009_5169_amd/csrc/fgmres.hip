@@ -431,7 +431,8 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
     f.data += (size_t)j * fch;
     return f;
   };
-  const Shape sh = default_shape(n);
+  Shape sh;
+  if (int rc0 = fp64_hop_shape(h, n, st, &sh)) return cleanup(), rc0;
   HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n);
   a.coef = -h->lat.kappa;
   // out = D^+ D in (FP64), t64 scratch
