@@ -102,6 +102,10 @@ def main():
     ap.add_argument("--bw-dims", default="32,32,32,64")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the batch, FP16 and learned-preconditioner measurements")
+    ap.add_argument("--rows", default="fp16,learned,batch",
+                    help="which comparison rows to run (comma list of fp16, learned, batch)")
+    ap.add_argument("--rows-only", action="store_true",
+                    help="run only the comparison rows (no bench step), for kernel traces of them")
     ap.add_argument("--profile-big", action="store_true",
                     help="with --profile-kernels: also the bandwidth lattice, 1 and 5 RHS")
     ap.add_argument("--order-ab", action="store_true",
@@ -125,6 +129,9 @@ def main():
     p = synth.CONFIG_1
     if args.profile_kernels:
         profile_kernels(args, synth, mfq, torch, dev, np)
+        return
+    if args.rows_only:
+        print(json.dumps({"rows": run_rows(args, synth, mfq, torch, dev, np)}))
         return
     u = p.links()
     phi_h = p.rhs()
@@ -219,10 +226,7 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_rows:
-        out["rows"] = {}
-        out["rows"]["fp16_16x16x16x16"] = bench_fp16(synth, mfq, torch, dev, np)
-        out["rows"]["learned_16x16x16x16"] = bench_learned(synth, mfq, torch, dev, np)
-        out["rows"]["batch_64_lattices"] = bench_batch(synth, mfq, torch, dev, np)
+        out["rows"] = run_rows(args, synth, mfq, torch, dev, np)
 
     if not args.no_cpu_baseline:
         from oracle import force as fmod
@@ -243,6 +247,19 @@ def main():
                                          "FP64 CG solves (normal equations, tol 1e-10) and the force"}
     lat.close()
     print(json.dumps(out))
+
+
+def run_rows(args, synth, mfq, torch, dev, np):
+    """The comparison rows named by --rows."""
+    rows = set(args.rows.split(","))
+    out = {}
+    if "fp16" in rows:
+        out["fp16_16x16x16x16"] = bench_fp16(synth, mfq, torch, dev, np)
+    if "learned" in rows:
+        out["learned_16x16x16x16"] = bench_learned(synth, mfq, torch, dev, np)
+    if "batch" in rows:
+        out["batch_64_lattices"] = bench_batch(synth, mfq, torch, dev, np)
+    return out
 
 
 def _timed(fn, reps=3):

@@ -204,12 +204,16 @@ __device__ __forceinline__ bool solve_column(double (&mr)[N][N], double (&mi)[N]
     const double pr = mr[k][k], pi = mi[k][k];
     const double pd = pr * pr + pi * pi;
     ok = ok && pd > 0.0 && isfinite(pd);
+    const double ipd = 1.0 / pd;  // 1 / M[k][k] = (pr - i pi) / pd
+    const double qr = pr * ipd, qi = -pi * ipd;
+    mr[k][k] = qr;  // keep the reciprocal pivot for the back substitution
+    mi[k][k] = qi;
 #pragma unroll
     for (int i = k + 1; i < N; ++i) {
       const double xr = mr[i][k], xi = mi[i][k];
-      const double fr = (xr * pr + xi * pi) / pd, fi = (xi * pr - xr * pi) / pd;  // M[i][k] / M[k][k]
+      const double fr = xr * qr - xi * qi, fi = xr * qi + xi * qr;  // M[i][k] / M[k][k]
 #pragma unroll
-      for (int c = k; c < N; ++c) {
+      for (int c = k + 1; c < N; ++c) {
         mr[i][c] -= fr * mr[k][c] - fi * mi[k][c];
         mi[i][c] -= fr * mi[k][c] + fi * mr[k][c];
       }
@@ -225,10 +229,9 @@ __device__ __forceinline__ bool solve_column(double (&mr)[N][N], double (&mi)[N]
       sr -= mr[k][l] * vr[l] - mi[k][l] * vi[l];
       si -= mr[k][l] * vi[l] + mi[k][l] * vr[l];
     }
-    const double pr = mr[k][k], pi = mi[k][k];
-    const double pd = pr * pr + pi * pi;
-    vr[k] = (sr * pr + si * pi) / pd;
-    vi[k] = (si * pr - sr * pi) / pd;
+    const double qr = mr[k][k], qi = mi[k][k];  // reciprocal pivot
+    vr[k] = sr * qr - si * qi;
+    vi[k] = sr * qi + si * qr;
     ok = ok && isfinite(vr[k]) && isfinite(vi[k]);
   }
   return ok;
