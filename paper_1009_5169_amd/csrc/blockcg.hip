@@ -11,8 +11,9 @@
 // right-hand sides (block BiCGStab on D in Sec. 3.1; this is the CG
 // counterpart on the normal equations).
 //
-// Thread mapping: one thread per (site, spin) of all n columns (grid.y =
-// spin), so a thread holds 3 colour components of each column at a time.
+// Thread mapping: one thread per (site, component) of all n columns (grid.y =
+// the 12 spin-colour components), so a thread holds one complex number of
+// each column.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -40,16 +41,16 @@ enum : int { BCG_INIT = 0, BCG_ALPHA = 1, BCG_BETA = 2 };
 // upper-triangle index of (i, j), i <= j
 __host__ __device__ constexpr int tri(int i, int j, int n) { return i * n - i * (i - 1) / 2 + (j - i); }
 
-__device__ __forceinline__ void load3(const Field<double>& f, int rhs, int par, int sp, int c, int s, cpx<double>& v) {
-  const d2 q = f.data[f.cidx(rhs, par, 3 * sp + c, s)];
+__device__ __forceinline__ void load1(const Field<double>& f, int rhs, int par, int comp, int s, cpx<double>& v) {
+  const d2 q = f.data[f.cidx(rhs, par, comp, s)];
   v = {q.x, q.y};
 }
-__device__ __forceinline__ void store3(const Field<double>& f, int rhs, int par, int sp, int c, int s,
+__device__ __forceinline__ void store1(const Field<double>& f, int rhs, int par, int comp, int s,
                                        const cpx<double>& v) {
   d2 q;
   q.x = v.re;
   q.y = v.im;
-  f.data[f.cidx(rhs, par, 3 * sp + c, s)] = q;
+  f.data[f.cidx(rhs, par, comp, s)] = q;
 }
 
 // One workgroup's partial of an upper-triangular Gram matrix (NE complex
@@ -73,7 +74,7 @@ __device__ __forceinline__ void bcg_block_partial(const double (&acc)[NV], doubl
 
 #define BCG_LANE                                          \
   const int q = blockIdx.x * blockDim.x + threadIdx.x;    \
-  const int sp = blockIdx.y;                              \
+  const int comp = blockIdx.y;                            \
   const bool valid = q < 2 * g.vh;                        \
   const int par = q >= g.vh ? 1 : 0;                      \
   const int s = valid ? q - par * g.vh : 0;
@@ -87,23 +88,20 @@ __global__ __launch_bounds__(256) void bcg_gram_kernel(Geom g, Field<double> A, 
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   if (valid) {
+    cpx<double> a[N], b[N];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      cpx<double> a[N], b[N];
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        load3(A, i, par, sp, c, s, a[i]);
-        load3(B, i, par, sp, c, s, b[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int j = i; j < N; ++j) {
-          const cpx<double> d = cjmul(a[i], b[j]);
-          acc[2 * tri(i, j, N)] += d.re;
-          acc[2 * tri(i, j, N) + 1] += d.im;
-        }
+    for (int i = 0; i < N; ++i) {
+      load1(A, i, par, comp, s, a[i]);
+      load1(B, i, par, comp, s, b[i]);
     }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        const cpx<double> d = cjmul(a[i], b[j]);
+        acc[2 * tri(i, j, N)] += d.re;
+        acc[2 * tri(i, j, N) + 1] += d.im;
+      }
   }
   bcg_block_partial<NV>(acc, part);
 }
@@ -118,37 +116,34 @@ __global__ __launch_bounds__(256) void bcg_xr_kernel(Geom g, Field<double> X, Fi
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   if (valid) {
+    cpx<double> p[N], qq[N], r[N];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      cpx<double> p[N], qq[N], r[N];
+    for (int j = 0; j < N; ++j) {
+      load1(P, j, par, comp, s, p[j]);
+      load1(Q, j, par, comp, s, qq[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      cpx<double> x;
+      load1(X, i, par, comp, s, x);
+      load1(R, i, par, comp, s, r[i]);
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        load3(P, j, par, sp, c, s, p[j]);
-        load3(Q, j, par, sp, c, s, qq[j]);
+        const cpx<double> al = {st->ar[j * BCG_MAXN + i], st->ai[j * BCG_MAXN + i]};
+        x = x + cmul(p[j], al);
+        r[i] = r[i] - cmul(qq[j], al);
       }
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        cpx<double> x;
-        load3(X, i, par, sp, c, s, x);
-        load3(R, i, par, sp, c, s, r[i]);
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          const cpx<double> al = {st->ar[j * BCG_MAXN + i], st->ai[j * BCG_MAXN + i]};
-          x = x + cmul(p[j], al);
-          r[i] = r[i] - cmul(qq[j], al);
-        }
-        store3(X, i, par, sp, c, s, x);
-        store3(R, i, par, sp, c, s, r[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int j = i; j < N; ++j) {
-          const cpx<double> d = cjmul(r[i], r[j]);
-          acc[2 * tri(i, j, N)] += d.re;
-          acc[2 * tri(i, j, N) + 1] += d.im;
-        }
+      store1(X, i, par, comp, s, x);
+      store1(R, i, par, comp, s, r[i]);
     }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        const cpx<double> d = cjmul(r[i], r[j]);
+        acc[2 * tri(i, j, N)] += d.re;
+        acc[2 * tri(i, j, N) + 1] += d.im;
+      }
   }
   bcg_block_partial<NV>(acc, part);
 }
@@ -159,19 +154,16 @@ __global__ __launch_bounds__(256) void bcg_p_kernel(Geom g, Field<double> R, Fie
                                                     const BcgState* st) {
   BCG_LANE
   if (!valid) return;
+  cpx<double> p[N];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    cpx<double> p[N];
+  for (int j = 0; j < N; ++j) load1(P, j, par, comp, s, p[j]);
 #pragma unroll
-    for (int j = 0; j < N; ++j) load3(P, j, par, sp, c, s, p[j]);
+  for (int i = 0; i < N; ++i) {
+    cpx<double> v;
+    load1(R, i, par, comp, s, v);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      cpx<double> v;
-      load3(R, i, par, sp, c, s, v);
-#pragma unroll
-      for (int j = 0; j < N; ++j) v = v + cmul(p[j], cpx<double>{st->br[j * BCG_MAXN + i], st->bi[j * BCG_MAXN + i]});
-      store3(Pn, i, par, sp, c, s, v);
-    }
+    for (int j = 0; j < N; ++j) v = v + cmul(p[j], cpx<double>{st->br[j * BCG_MAXN + i], st->bi[j * BCG_MAXN + i]});
+    store1(Pn, i, par, comp, s, v);
   }
 }
 
@@ -365,14 +357,12 @@ __global__ __launch_bounds__(256) void bcg_combine_kernel(Geom g, Field<double> 
                                                           Field<double> out, int n, int sub) {
   BCG_LANE
   if (!valid) return;
-  for (int i = 0; i < n; ++i)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      cpx<double> x, y;
-      load3(a, i, par, sp, c, s, x);
-      load3(b, i, par, sp, c, s, y);
-      store3(out, i, par, sp, c, s, sub ? x - y : x + y);
-    }
+  for (int i = 0; i < n; ++i) {
+    cpx<double> x, y;
+    load1(a, i, par, comp, s, x);
+    load1(b, i, par, comp, s, y);
+    store1(out, i, par, comp, s, sub ? x - y : x + y);
+  }
 }
 
 #define BCG_N_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
@@ -448,8 +438,8 @@ int run_block_cg(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
     release(partb);
   };
   const int nblk = (2 * g.vh + 255) / 256;
-  const dim3 grid(nblk, 4);
-  const int nparts = nblk * 4;
+  const dim3 grid(nblk, 12);
+  const int nparts = nblk * 12;
   if (fr.alloc(g, n) || fp.alloc(g, n) || fq.alloc(g, n) || fpn.alloc(g, n) || ensure(stb, sizeof(BcgState)) ||
       ensure(partb, sizeof(double) * (size_t)nparts * n * (n + 1))) {
     cleanup();
