@@ -119,7 +119,7 @@ typedef struct {
   int prec;              /* mfq_prec                                          */
   double reliable_delta; /* reliable-update trigger (<= 0: default 0.1)      */
   int precond;           /* mfq_pc                                            */
-  int restart;           /* FGMRES restart length (PTC only; <= 0: 16)        */
+  int restart;           /* FGMRES restart length (PTC / IDENTITY; <= 0: 16)  */
   int check_every;       /* iterations between host polls (<= 0: default)    */
   int use_graph;         /* capture the inner iterations in a hipGraph        */
 } mfq_solve_params;

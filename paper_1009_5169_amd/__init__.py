@@ -78,7 +78,12 @@ class Lattice:
         return out
 
     def solve(self, b: torch.Tensor, params=None, stream=None, **kw):
-        """x = (D^+D)^-1 b for all RHS at once; returns (x, [stats dicts], status)."""
+        """x = (D^+D)^-1 b for all RHS at once; returns (x, [stats dicts], status).
+
+        Keyword arguments go to make_params: tol, max_iter, prec ("fp64", "fp32",
+        "fp16"), reliable_delta, precond ("none": batched CG; "blockcg": block CG,
+        FP64, at most 8 RHS; "ptc" / "identity": FGMRES with / without the learned
+        preconditioner), restart, check_every, use_graph."""
         n = self._check_spinor(b)
         p = params if params is not None else make_params(**kw)
         x = torch.empty_like(b)
