@@ -1,0 +1,85 @@
+"""GPU parity at the full size of the comparison rows (16^3x16 SF, 5 RHS), in
+the launch configurations the benchmark times (the shipped tuning table).
+
+At this size the oracle is the compiled FP64 reference operator (oracle/native)
+and the numpy network: every solution's residual is re-measured with the
+oracle's D^+D, the FP64 operator is compared element by element, and the
+network application is compared with the oracle's forward pass.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import native, ptc
+from oracle.dirac import WilsonDirac
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1009_5169_amd as mfq  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_full_size_solves_and_operator():
+    p = synth.CONFIG_2
+    u = p.links()
+    b = p.rhs()
+    lat = mfq.Lattice(p.dims, p.bc, p.kappa, to_dev(u))
+    d = native.NativeWilson(p.dims, p.bc, p.kappa, u)
+    got = to_host(lat.dslash("D", to_dev(b)))
+    err = rel(got, d.D(b))
+    note(f"{p.name}: FP64 D rel err {err:.2e}")
+    assert err < 1e-13
+    for prec, pc in (("fp64", "none"), ("fp32", "none"), ("fp16", "none"), ("fp64", "blockcg")):
+        x, st, rc = lat.solve(to_dev(b), tol=1e-10, prec=prec, precond=pc, max_iter=20000)
+        assert rc == 0, (prec, pc, st)
+        x = to_host(x)
+        r = b - d.DdagD(x)
+        res = [float(np.linalg.norm(r[i]) / np.linalg.norm(b[i])) for i in range(p.n_rhs)]
+        note(f"{p.name} {prec} {pc}: iters {[s['iters'] for s in st]} oracle residuals "
+             + ", ".join("%.2e" % v for v in res))
+        assert max(res) <= 1.05e-10
+    lat.close()
+
+
+def test_full_size_network_application():
+    """The matrix-core network on a 16^3x16 field against the oracle's
+    forward pass with the same BF16-valued weights."""
+    p = synth.CONFIG_4
+    u = p.links()
+    lat = mfq.Lattice(p.dims, p.bc, p.kappa, to_dev(u))
+    lat.precond_init(seed=5)
+    w = lat.precond_get_weights("inference")
+    w1 = w[: 9 * 8 * 16].reshape(9, 8, 4, 4)[:, :, None]
+    w2 = w[9 * 8 * 16:].reshape(9, 8, 4, 4)[:, None]
+    r = synth.gaussian_spinors(p.dims, p.bc, 1, 2500)
+    got = to_host(lat.precond_apply(to_dev(r)))
+    want, _ = ptc.forward(ptc.Transport(WilsonDirac(p.dims, p.bc, p.kappa, u)), w1, w2, r)
+    err = rel(got, want)
+    note(f"{p.name}: network application rel err {err:.2e}")
+    assert err < 2e-5
+    lat.close()
