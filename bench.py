@@ -385,15 +385,23 @@ def bench_batch(synth, mfq, torch, dev, np):
     return res
 
 
-def bandwidth_lattice(dims, synth, mfq, torch, dev, np):
-    """Periodic lattice for the bandwidth runs: random SU(3) links on a 16^3 x 8
-    block, tiled over the lattice (the values do not matter for bandwidth and
-    numpy's 3x3 eigh is slow)."""
+def bandwidth_links(dims, synth, np):
+    """Links of the bandwidth lattice (periodic): random SU(3) links on a
+    16^3 x 8 block, tiled over the lattice (the values do not matter for
+    bandwidth and numpy's 3x3 eigh is slow)."""
     blk = (min(16, dims[0]), min(16, dims[1]), min(16, dims[2]), min(8, dims[3]))
     ub = synth.random_links(blk, "periodic", 0.3, 7)
     reps = (1, dims[3] // blk[3], dims[2] // blk[2], dims[1] // blk[1], dims[0] // blk[0], 1, 1)
-    ub = np.ascontiguousarray(np.tile(ub, reps))
-    return mfq.Lattice(dims, "periodic", 0.12, torch.from_numpy(ub).to(dev))
+    return np.ascontiguousarray(np.tile(ub, reps))
+
+
+BANDWIDTH_KAPPA = 0.12
+
+
+def bandwidth_lattice(dims, synth, mfq, torch, dev, np):
+    """The bandwidth lattice as a library handle."""
+    ub = bandwidth_links(dims, synth, np)
+    return mfq.Lattice(dims, "periodic", BANDWIDTH_KAPPA, torch.from_numpy(ub).to(dev))
 
 
 def profile_kernels(args, synth, mfq, torch, dev, np):

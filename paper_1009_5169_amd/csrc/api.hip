@@ -125,9 +125,11 @@ int pack_checked(mfq_handle* h, const double* canon, int n_rhs, int gamma5, hipS
 
 // out = op(in) in storage S; tmp is scratch (DDAGD only).  Fields are views.
 template <typename S>
-int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field<S> out, int n_rhs,
+int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field<S> out, int n_rhs, Shape sh2,
              hipStream_t st) {
-  const Shape sh = default_shape(n_rhs);
+  // both-parity launches take sh2 (the solver's tuned shape for this
+  // precision); single-parity ones the default shape
+  const Shape sh1 = default_shape(n_rhs);
   const double mk = -h->lat.kappa;
   HopArgs<S, S> a = hop_args<S, S>(h, L, n_rhs);
   auto run = [&](int epi, Field<S> src, Field<S> dst, int par, int dag, double coef) -> hipError_t {
@@ -137,7 +139,7 @@ int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field
     a.par = par;
     a.dagger = dag;
     a.coef = coef;
-    return launch_hop<S, S>(epi, a, sh, st);
+    return launch_hop<S, S>(epi, a, par == 2 ? sh2 : sh1, st);
   };
   switch (op) {
     case MFQ_OP_HOP_EO:
@@ -657,21 +659,26 @@ int mfq_dslash_prec(mfq_handle* h, int op, int prec, const double* in_dev, doubl
   const Geom& g = h->g;
   const Shape sh = default_shape(n_rhs);
   HIPCHK(launch_pack_spinor<double>(g, in_dev, w.b64.view(g), n_rhs, 0, nullptr, st));
+  Shape sh2;
   if (prec == MFQ_PREC_FP64) {
-    rc = apply_op<double>(h, op, links_d(h), w.b64.view(g), w.t64.view(g), w.r64.view(g), n_rhs, st);
+    if ((rc = fp64_hop_shape(h, n_rhs, st, &sh2))) return rc;
+    rc = apply_op<double>(h, op, links_d(h), w.b64.view(g), w.t64.view(g), w.r64.view(g), n_rhs, sh2, st);
   } else if (prec == MFQ_PREC_FP32_RELIABLE) {
     HIPCHK(w.rs.alloc(g, n_rhs));
     HIPCHK(w.ps.alloc(g, n_rhs));
     HIPCHK(w.ts.alloc(g, n_rhs));
+    if ((rc = tuned_shape<float, float>(h, n_rhs, 4, links_f(h), w.ts.view(g), w.ps.view(g), st, &sh2))) return rc;
     HIPCHK(launch_convert<double, float>(g, w.b64.view(g), w.rs.view(g), 0, n_rhs, sh, st));
-    rc = apply_op<float>(h, op, links_f(h), w.rs.view(g), w.ts.view(g), w.ps.view(g), n_rhs, st);
+    rc = apply_op<float>(h, op, links_f(h), w.rs.view(g), w.ts.view(g), w.ps.view(g), n_rhs, sh2, st);
     if (!rc) HIPCHK(launch_convert<float, double>(g, w.ps.view(g), w.r64.view(g), 0, n_rhs, sh, st));
   } else {
     HIPCHK(w.rh.alloc(g, n_rhs));
     HIPCHK(w.ph.alloc(g, n_rhs));
     HIPCHK(w.th.alloc(g, n_rhs));
+    if ((rc = tuned_shape<_Float16, float>(h, n_rhs, 2, links_h(h), w.th.view(g), w.ph.view(g), st, &sh2)))
+      return rc;
     HIPCHK(launch_convert<double, _Float16>(g, w.b64.view(g), w.rh.view(g), 0, n_rhs, sh, st));
-    rc = apply_op<_Float16>(h, op, links_h(h), w.rh.view(g), w.th.view(g), w.ph.view(g), n_rhs, st);
+    rc = apply_op<_Float16>(h, op, links_h(h), w.rh.view(g), w.th.view(g), w.ph.view(g), n_rhs, sh2, st);
     if (!rc) HIPCHK(launch_convert<_Float16, double>(g, w.ph.view(g), w.r64.view(g), 0, n_rhs, sh, st));
   }
   if (rc) return rc;

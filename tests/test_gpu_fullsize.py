@@ -83,3 +83,21 @@ def test_full_size_network_application():
     note(f"{p.name}: network application rel err {err:.2e}")
     assert err < 2e-5
     lat.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+def test_bandwidth_lattice_operator(prec, tol):
+    """D on the 32^3x64 periodic lattice of the benchmark's bandwidth runs, one
+    RHS, in the launch shape the benchmark times (the tuned shape of the
+    solver's hopping kernel), against the compiled oracle over every site."""
+    import bench
+    dims = (32, 32, 32, 64)
+    u = bench.bandwidth_links(dims, synth, np)
+    lat = mfq.Lattice(dims, "periodic", bench.BANDWIDTH_KAPPA, to_dev(u))
+    x = synth.gaussian_spinors(dims, "periodic", 1, 2600)
+    got = to_host(lat.dslash("D", to_dev(x), prec=prec))
+    want = native.NativeWilson(dims, "periodic", bench.BANDWIDTH_KAPPA, u).D(x)
+    err = rel(got, want)
+    note(f"32^3x64 {prec} D (shape {lat.hop_shape(prec, 1)}): rel err {err:.2e}")
+    assert err < tol
+    lat.close()
