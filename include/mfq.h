@@ -255,7 +255,8 @@ int mfq_set_autotune(mfq_handle* h, int on);
 /* The shape the inner solver uses for (precision, n_rhs): shape5 (host, 5
  * ints) receives {sites per workgroup, RHS per workgroup, tile order flags
  * (bit 0: each XCD walks a contiguous chunk of tiles; bit 1: tiles walked
- * (z, t) plane by plane over blocks of consecutive z, t before z),
+ * (z, t) plane by plane over blocks of consecutive z, t before z; bit 2: the
+ * workgroup's links staged in an LDS tile shared by its RHS rows),
  * time-sweep length (0: one site per thread; else each thread walks that many
  * time slices of one spatial site, sites per workgroup then counting spatial
  * sites), direction split (0, or 2 / 4 wavefronts sharing the 4 directions of

@@ -114,9 +114,9 @@ class Lattice:
         _lib.check(_lib.lib().mfq_set_autotune(self._h, int(bool(on))))
 
     def hop_shape(self, prec: str, n_rhs: int):
-        """(sites per workgroup, RHS per workgroup, tile order flags (bit 0 XCD
-        remap, bit 1 z-blocked order), time-sweep length, direction split) of
-        the inner solver's hopping kernel."""
+        """(sites per workgroup, RHS per workgroup, order flags (bit 0 XCD
+        remap, bit 1 z-blocked order, bit 2 LDS link tile), time-sweep length,
+        direction split) of the inner solver's hopping kernel."""
         out = (ctypes.c_int * 5)()
         _lib.check(_lib.lib().mfq_hop_shape(self._h, PREC[prec], int(n_rhs), out))
         return tuple(out)

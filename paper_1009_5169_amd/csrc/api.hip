@@ -221,7 +221,7 @@ bool tune_cache_lookup(mfq_handle* h, int n, int prec, Shape* out) {
                      nr * (ds - 1) * 24 * 64 * (prec == 8 ? 8 : 4) <= 65536))) {
       out->sb = sb;
       out->nr = nr;
-      out->xcd = xcd & 3;
+      out->xcd = xcd & 7;
       out->tc = tc;
       out->ds = ds;
       found = true;
@@ -252,12 +252,15 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
       if (nr > n || sb * nr > 512 || (k > 0 && nr == nrs[k - 1])) continue;
       for (int tc = 0; tc <= 4; tc += 4) {  // the time sweep measured slower so far: one candidate
         if (tc >= 2 * h->g.td) continue;  // one chunk already covers the time extent
-        for (int xcd = 0; xcd < 4; ++xcd) {
+        for (int xcd = 0; xcd < 8; ++xcd) {
           if ((xcd & 2) && tc) continue;  // the time sweep has its own order
+          // LDS link tile: two-row links, several RHS rows, the plain kernel, <= 64 KB
+          if ((xcd & 4) && (prec == 8 || nr < 2 || tc || 24 * sb * (prec == 4 ? 16 : 8) > 65536)) continue;
           for (int ds = 0; ds <= 4; ds += 2) {
             // split: 64 sites x nr RHS, ds * nr waves, partial hopping terms in LDS
             if (ds && (sb != 64 || ds * nr > 8 || tc || nr * (ds - 1) * 24 * 64 * (prec == 8 ? 8 : 4) > 65536))
               continue;
+            if (ds && (xcd & 4)) continue;  // the LDS link tile is a form of the plain kernel
             Shape sh{sb, nr, xcd, tc, ds};
             for (int i = 0; i < 2; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
             HIPCHK(hipEventRecord(h->ev0, st));

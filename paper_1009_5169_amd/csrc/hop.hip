@@ -85,17 +85,22 @@ __device__ __forceinline__ double alpha_finish(const HopArgs<S, SX>& a, int r, i
 // parity over the same half-index range: the two tiles share the links of
 // their rows (the forward link of one parity is the backward link of the
 // other) and each other's spinors, so they meet in the same XCD's L2.
-template <int EPI, typename S, typename SX>
+//
+// With LDSL (FP32 / FP16 links) the workgroup first copies the 4 forward and
+// 4 backward links of each of its sites into LDS, and every RHS row of the
+// workgroup reads them from there: one link load serves all its RHS.
+template <int EPI, typename S, typename SX, bool LDSL = false>
 __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
   const int tile = tile_index(a.xcd);
   int par = a.par;
-  int s;
+  int s0;
   if (par == 2) {
     par = tile & 1;
-    s = tile_site0(a, tile >> 1, blockDim.x) + threadIdx.x;
+    s0 = tile_site0(a, tile >> 1, blockDim.x);
   } else {
-    s = tile_site0(a, tile, blockDim.x) + threadIdx.x;
+    s0 = tile_site0(a, tile, blockDim.x);
   }
+  const int s = s0 + threadIdx.x;
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
   double av = 0.0;
   if constexpr (EPI == EPI_CGUPD) av = alpha_fetch(a, r, threadIdx.x < 64);
@@ -104,7 +109,37 @@ __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
   using T = typename Compute<S>::T;
   Spinor<T> acc;
   zero(acc);
-  if (active) hop_dirs<0, 4>(a, par, s, site_coords(a.g, s, par), r, acc);
+  if constexpr (LDSL) {
+    using C = typename LinkChunk<S>::type;
+    extern __shared__ __align__(16) unsigned char lds_link_tile[];
+    C* tl = (C*)lds_link_tile;
+    const int sb = blockDim.x;
+    const C* gl = (const C*)a.links.data;
+    // element e = lane + sb (chunk + 3 slot)
+    for (int e = threadIdx.y * sb + threadIdx.x; e < 24 * sb; e += sb * blockDim.y) {
+      const int lane = e % sb, k = (e / sb) % 3, slot = e / (3 * sb), mu = slot & 3;
+      const int sl = s0 + lane;
+      C v;
+      v.x = v.y = v.z = v.w = 0;
+      if (sl < a.g.vh) {
+        if (slot < 4) {
+          v = gl[a.links.cidx(par, mu, k, sl)];
+        } else {
+          const Coords cl = site_coords(a.g, sl, par);
+          const int sbk = mu == 0   ? back_neighbour<0>(a.g, cl)
+                          : mu == 1 ? back_neighbour<1>(a.g, cl)
+                          : mu == 2 ? back_neighbour<2>(a.g, cl)
+                                    : back_neighbour<3>(a.g, cl);
+          v = gl[a.links.cidx(1 - par, mu, k, sbk)];
+        }
+      }
+      tl[e] = v;
+    }
+    __syncthreads();
+    if (active) hop_dirs_with<0, 4>(a, LdsLinks<S>{tl, sb, (int)threadIdx.x}, par, s, site_coords(a.g, s, par), r, acc);
+  } else {
+    if (active) hop_dirs<0, 4>(a, par, s, site_coords(a.g, s, par), r, acc);
+  }
   double alpha = 0.0;
   if constexpr (EPI == EPI_CGUPD) alpha = alpha_finish(a, r, threadIdx.y, threadIdx.x < 64, av);
   const double red = active ? hop_epilogue<EPI>(a, par, s, r, alpha, acc) : 0.0;
@@ -253,7 +288,7 @@ int max_hop_blocks(const Geom& g) {
 template <typename S, typename SX>
 hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st) {
   HopArgs<S, SX> b = a;
-  b.xcd = sh.xcd & 1;
+  b.xcd = sh.xcd & 1;  // bit 1: z-blocked order (below); bit 2: LDS link tile (plain kernel)
   b.zb = 0;
   b.tpp = 0;
   {
@@ -312,6 +347,21 @@ hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+  }
+  if constexpr (sizeof(S) != 8) {
+    // LDS link tile (order flag bit 2): 24 chunks per site
+    const size_t lds_bytes = (size_t)24 * sh.sb * sizeof(typename LinkChunk<S>::type);
+    if ((sh.xcd & 4) && lds_bytes <= 65536) {
+      switch (epi) {
+        case EPI_HOP: hipLaunchKernelGGL((hop_kernel<EPI_HOP, S, SX, true>), grid, block, lds_bytes, st, b); break;
+        case EPI_D: hipLaunchKernelGGL((hop_kernel<EPI_D, S, SX, true>), grid, block, lds_bytes, st, b); break;
+        case EPI_CGUPD:
+          hipLaunchKernelGGL((hop_kernel<EPI_CGUPD, S, SX, true>), grid, block, lds_bytes, st, b);
+          break;
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
   }
   switch (epi) {
     case EPI_HOP: hipLaunchKernelGGL((hop_kernel<EPI_HOP, S, SX>), grid, block, 0, st, b); break;

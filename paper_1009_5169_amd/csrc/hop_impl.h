@@ -59,6 +59,62 @@ struct PlainSrc {
   __device__ __forceinline__ void load(int r, int par, int s, Spinor<T>& o) const { load_spinor(f, r, par, s, o); }
 };
 
+// Where the hopping term reads its links: the global arrays, or an LDS tile
+// holding, for each site of the workgroup's tile, its 4 forward links U_mu(n)
+// and 4 backward links U_mu(n - mu) (two-row FP32 / FP16 storage), filled
+// once per workgroup and read by every RHS row.
+template <typename S>
+struct GlobalLinks {
+  Links<S> L;
+  template <int MU, typename T>
+  __device__ __forceinline__ void fwd(int par, int s, cpx<T> u[9]) const { load_link(L, par, MU, s, u); }
+  template <int MU, typename T>
+  __device__ __forceinline__ void bwd(int po, int sbk, cpx<T> u[9]) const { load_link(L, po, MU, sbk, u); }
+};
+
+template <typename S>
+struct LinkChunk;
+template <>
+struct LinkChunk<float> {
+  using type = f4;
+};
+template <>
+struct LinkChunk<_Float16> {
+  using type = h4;
+};
+
+template <typename S>
+struct LdsLinks {
+  const typename LinkChunk<S>::type* tile;  // [slot 0..7][3 chunks][sb]: slot mu forward, 4 + mu backward
+  int sb, lane;
+  template <int SLOT, typename T>
+  __device__ __forceinline__ void get(cpx<T> u[9]) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const auto q = tile[(SLOT * 3 + k) * sb + lane];
+      u[2 * k] = {(T)(float)q.x, (T)(float)q.y};
+      u[2 * k + 1] = {(T)(float)q.z, (T)(float)q.w};
+    }
+    third_row(u);
+  }
+  template <int MU, typename T>
+  __device__ __forceinline__ void fwd(int, int, cpx<T> u[9]) const { get<MU>(u); }
+  template <int MU, typename T>
+  __device__ __forceinline__ void bwd(int, int, cpx<T> u[9]) const { get<4 + MU>(u); }
+};
+
+// The backward neighbour of coordinates c in direction MU (half-lattice
+// index, always inside the lattice; the boundary factor is not needed here).
+template <int MU>
+__device__ __forceinline__ int back_neighbour(const Geom& g, const Coords& c) {
+  int x = c.x, y = c.y, z = c.z, t = c.t;
+  if constexpr (MU == 0) t = c.t == 0 ? g.td - 1 : c.t - 1;
+  else if constexpr (MU == 1) x = c.x == 0 ? g.lx - 1 : c.x - 1;
+  else if constexpr (MU == 2) y = c.y == 0 ? g.ly - 1 : c.y - 1;
+  else z = c.z == 0 ? g.lz - 1 : c.z - 1;
+  return half_index(g, x, y, z, t);
+}
+
 // One direction mu of the hopping term: forward hop from n+mu through U_mu(n),
 // backward hop from n-mu through U_mu(n-mu)^+.  sgf / sgb are the projector
 // signs (-1 / +1 for H, +1 / -1 for H^+).  The time boundary is folded into a
@@ -66,9 +122,9 @@ struct PlainSrc {
 // antiperiodic wrap) on a neighbour index that always stays inside the
 // lattice, so the loads of every direction are unconditional and can be
 // issued together.
-template <int MU, typename S, typename SX, typename T, typename Src>
-__device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Src& src, int par, const Coords& c, int s,
-                                        int r, T sgf, T sgb, Spinor<T>& acc) {
+template <int MU, typename S, typename SX, typename T, typename Src, typename LS>
+__device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Src& src, const LS& lk, int par,
+                                        const Coords& c, int s, int r, T sgf, T sgb, Spinor<T>& acc) {
   const Geom& g = a.g;
   const int po = 1 - par;
   int xf = c.x, yf = c.y, zf = c.z, tf = c.t;
@@ -101,9 +157,9 @@ __device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Src& src,
   Spinor<T> nf, nb;
   cpx<T> uf[9], ub[9];
   src.load(r, po, sf, nf);
-  load_link(a.links, par, MU, s, uf);
+  lk.template fwd<MU>(par, s, uf);
   src.load(r, po, sbk, nb);
-  load_link(a.links, po, MU, sbk, ub);
+  lk.template bwd<MU>(po, sbk, ub);
   {  // forward
     cpx<T> h0[3], h1[3];
 #pragma unroll
@@ -191,16 +247,22 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
 
 
 // Directions [MU0, MU1) of the hopping term at output site s, accumulated into acc.
-template <int MU0, int MU1, typename S, typename SX, typename T>
-__device__ __forceinline__ void hop_dirs(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
-                                         Spinor<T>& acc) {
+template <int MU0, int MU1, typename S, typename SX, typename T, typename LS>
+__device__ __forceinline__ void hop_dirs_with(const HopArgs<S, SX>& a, const LS& lk, int par, int s,
+                                              const Coords& c, int r, Spinor<T>& acc) {
   const T sgf = a.dagger ? (T)1 : (T)-1;
   const T sgb = -sgf;
   PlainSrc<S, T> src{a.in};
-  if constexpr (MU0 <= 0 && 0 < MU1) hop_dir<0>(a, src, par, c, s, r, sgf, sgb, acc);
-  if constexpr (MU0 <= 1 && 1 < MU1) hop_dir<1>(a, src, par, c, s, r, sgf, sgb, acc);
-  if constexpr (MU0 <= 2 && 2 < MU1) hop_dir<2>(a, src, par, c, s, r, sgf, sgb, acc);
-  if constexpr (MU0 <= 3 && 3 < MU1) hop_dir<3>(a, src, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 0 && 0 < MU1) hop_dir<0>(a, src, lk, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 1 && 1 < MU1) hop_dir<1>(a, src, lk, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 2 && 2 < MU1) hop_dir<2>(a, src, lk, par, c, s, r, sgf, sgb, acc);
+  if constexpr (MU0 <= 3 && 3 < MU1) hop_dir<3>(a, src, lk, par, c, s, r, sgf, sgb, acc);
+}
+
+template <int MU0, int MU1, typename S, typename SX, typename T>
+__device__ __forceinline__ void hop_dirs(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
+                                         Spinor<T>& acc) {
+  hop_dirs_with<MU0, MU1>(a, GlobalLinks<S>{a.links}, par, s, c, r, acc);
 }
 
 // The epilogue applied to the complete hopping term acc at output site s;

@@ -156,7 +156,7 @@ PREC_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [(64, 1, 0, 2, 0), (64, 3, 1, 4, 0), (128, 2, 0, 8, 0), (64, 1, 1, 16, 0),
                                    (128, 1, 0, 0, 0), (64, 3, 1, 0, 0), (64, 1, 0, 0, 2), (64, 1, 1, 0, 4),
-                                   (64, 3, 0, 0, 2), (64, 2, 1, 0, 2)],
+                                   (64, 3, 0, 0, 2), (64, 2, 1, 0, 2), (64, 3, 4, 0, 0), (128, 2, 5, 0, 0)],
                          ids=lambda s: "sb%d_nr%d_xcd%d_tc%d_ds%d" % s)
 def test_forced_launch_shapes_match_oracle(tmp_path, monkeypatch, shape, prec):
     """Every launch shape the autotuner may pick, forced through the tuning
@@ -185,7 +185,7 @@ def test_forced_launch_shapes_match_oracle(tmp_path, monkeypatch, shape, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [(64, 1, 2, 0, 0), (64, 3, 3, 0, 0), (64, 1, 2, 0, 4), (64, 2, 3, 0, 2),
-                                   (128, 1, 3, 0, 0)],
+                                   (128, 1, 3, 0, 0), (64, 3, 7, 0, 0)],
                          ids=lambda s: "sb%d_nr%d_xcd%d_tc%d_ds%d" % s)
 @pytest.mark.parametrize("lattice", [((8, 16, 6, 6), "sf"), ((8, 16, 4, 4), "periodic")],
                          ids=["sf8x16x6x6", "periodic8x16x4x4"])
@@ -214,6 +214,28 @@ def test_z_blocked_tile_order_matches_oracle(tmp_path, monkeypatch, lattice, sha
     x_ref, _ = solvers.cg_normal(d, b, 1e-14)
     c = _cond(d, b)
     assert rel(x, x_ref) <= c * (tol + 1e-14) + 1e-14, (rel(x, x_ref), c)
+    lat.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 3, 4, 0, 0), (256, 2, 6, 0, 0)],
+                         ids=lambda s: "sb%d_nr%d_xcd%d_tc%d_ds%d" % s)
+def test_lds_link_tile_fp16_matches_oracle(tmp_path, monkeypatch, shape):
+    """The LDS link tile (order flag bit 2) with FP16 storage: the FP16 links
+    staged in LDS (4-half chunks), FP64 defect correction to 1e-10."""
+    dims, bc, kappa, n, tol = (4, 6, 2, 10), "sf", 0.13, 3, 1e-10
+    key = "gfx950 %d %d %d %d %d %d %d" % (dims + (BC_CODE[bc], n, PREC_BYTES["fp16"]))
+    cache = tmp_path / "tune.txt"
+    cache.write_text(key + "|%d %d %d %d %d\n" % shape)
+    monkeypatch.setenv("MFQ_AUTOTUNE_CACHE", str(cache))
+    _, lat, d = make(dims, bc, kappa, 0.4, 1140)
+    b = synth.gaussian_spinors(dims, bc, n, 2140)
+    x, stats, rc = lat.solve(to_dev(b), tol=tol, prec="fp16", max_iter=5000)
+    assert tuple(lat.hop_shape("fp16", n)) == shape
+    assert rc == 0, stats
+    x = to_host(x)
+    for i in range(n):
+        res = np.linalg.norm(b[i:i + 1] - d.DdagD(x[i:i + 1])) / np.linalg.norm(b[i])
+        assert res <= tol * 1.05, (i, res)
     lat.close()
 
 
