@@ -44,12 +44,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(prec: str, n_rhs: int):
+def measured_traffic(prec: str, n_rhs: int, shape=None):
     """HBM-side bytes per launch of the roofline kernel from the committed
     counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
     what the counter reads for a plain copy of known size), or None when the
-    summary is missing, is for another precision / RHS count, or was taken
-    with different kernel sources."""
+    summary is missing, is for another precision / RHS count / launch shape,
+    or was taken with different kernel sources."""
     try:
         with open(COUNTERS_FILE) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
@@ -57,6 +57,8 @@ def measured_traffic(prec: str, n_rhs: int):
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("source_sha256") != kernel_source_hash() or kv.get("prec") != prec or int(kv.get("n_rhs", 0)) != n_rhs:
+        return None
+    if shape is not None and [int(v) for v in kv.get("launch_shape", "").split()] != [int(v) for v in shape]:
         return None
     copy_kib = float(kv["copy_bytes"]) / 1024.0
     fetch = float(kv["fetch_kib_per_dispatch"]) * copy_kib / float(kv["copy_fetch_kib"])
@@ -164,7 +166,7 @@ def main():
     per_launch = hop_bytes_per_site_rhs(args.prec, n) * vd * n
     achieved = per_launch / (hop_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.prec, n),
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.prec, n, shape),
                 "kernel": kernel_name(args.prec, shape), "launch_us": round(hop_ms * 1e3, 3),
                 "shape": list(shape),
                 "algorithmic_bytes_per_launch": int(per_launch)}

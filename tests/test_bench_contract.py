@@ -47,6 +47,8 @@ def test_counter_traffic_needs_the_current_kernel_sources(tmp_path, monkeypatch)
     copy_kib = 1073741824 / 1024.0
     want = (3297.5 * copy_kib / 524299.5 + 1688.8 * copy_kib / 1048576.0) * 1024
     assert got == int(round(want))
+    assert bench.measured_traffic("fp32", 5, (64, 1, 0, 0, 2)) == got
+    assert bench.measured_traffic("fp32", 5, (64, 5, 0, 0, 0)) is None  # another launch shape
     assert bench.measured_traffic("fp64", 5) is None          # another precision
     assert bench.measured_traffic("fp32", 1) is None          # another RHS count
     monkeypatch.setattr(bench, "COUNTERS_FILE", str(tmp_path / "missing.txt"))
