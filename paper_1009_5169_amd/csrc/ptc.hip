@@ -253,51 +253,62 @@ hipError_t ptc_adjoint2(const Geom& g, Links<float> L, Field<float> gy, Field<fl
   return hipGetLastError();
 }
 
-// One (path, c_out, c_in) weight-gradient block per blockIdx.y; each thread
-// sums its site's spin outer product over colours and pairs; the workgroup
-// reduces in FP64 and writes one partial per workgroup.
-template <typename SX>
+// Weight gradients: blockIdx.y = (path, c_in) and blockIdx.z a group of CO
+// output channels; each thread transports its site's input once per pair and
+// sums the spin outer products with the CO output gradients over colours and
+// pairs; the workgroup reduces in FP64 and writes one partial per (path,
+// c_out, c_in) block and workgroup.
+template <typename SX, int CO>
 __global__ __launch_bounds__(256) void ptc_wgrad_kernel(Geom g, Links<float> L, Field<SX> x, int c_in, Field<float> gf,
                                                         int c_out, int n_pairs, double* part) {
-  __shared__ double ws[4][32];
+  __shared__ double ws[4][CO * 32];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int idx = blockIdx.y;  // (p * c_out + co) * c_in + ci
-  const int ci = idx % c_in;
-  const int co = (idx / c_in) % c_out;
-  const int p = idx / (c_in * c_out);
-  float acc[32];
+  const int ci = blockIdx.y % c_in;
+  const int p = blockIdx.y / c_in;
+  const int co0 = blockIdx.z * CO;
+  float acc[CO][32];
 #pragma unroll
-  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+  for (int j = 0; j < CO; ++j)
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[j][k] = 0.f;
   if (q < 2 * g.vh) {
     const int par = q >= g.vh ? 1 : 0;
     const int s = q - par * g.vh;
     const Coords c = site_coords(g, s, par);
     for (int k = 0; k < n_pairs; ++k) {
-      Spinor<float> t, gg;
+      Spinor<float> t;
       transported(g, L, x, k * c_in + ci, p, s, par, c, t);
-      load_spinor(gf, k * c_out + co, par, s, gg);
 #pragma unroll
-      for (int so = 0; so < 4; ++so)
+      for (int j = 0; j < CO; ++j) {
+        Spinor<float> gg;
+        load_spinor(gf, k * c_out + co0 + j, par, s, gg);
 #pragma unroll
-        for (int si = 0; si < 4; ++si) {
-          cpx<float> o = {0.f, 0.f};
+        for (int so = 0; so < 4; ++so)
 #pragma unroll
-          for (int a = 0; a < 3; ++a) o = o + cjmul(t.v[3 * si + a], gg.v[3 * so + a]);
-          acc[2 * (4 * so + si)] += o.re;
-          acc[2 * (4 * so + si) + 1] += o.im;
-        }
+          for (int si = 0; si < 4; ++si) {
+            cpx<float> o = {0.f, 0.f};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) o = o + cjmul(t.v[3 * si + a], gg.v[3 * so + a]);
+            acc[j][2 * (4 * so + si)] += o.re;
+            acc[j][2 * (4 * so + si) + 1] += o.im;
+          }
+      }
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    const double v = wave_sum((double)acc[k]);
-    if (lane == 0) ws[wave][k] = v;
-  }
+  for (int j = 0; j < CO; ++j)
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const double v = wave_sum((double)acc[j][k]);
+      if (lane == 0) ws[wave][j * 32 + k] = v;
+    }
   __syncthreads();
-  if (threadIdx.x < 32) {
+  if (threadIdx.x < CO * 32) {
+    const int j = threadIdx.x / 32, k = threadIdx.x % 32;
     const double v = ((ws[0][threadIdx.x] + ws[1][threadIdx.x]) + ws[2][threadIdx.x]) + ws[3][threadIdx.x];
-    part[((long)idx * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = v;
+    const int idx = (p * c_out + co0 + j) * c_in + ci;
+    part[((long)idx * gridDim.x + blockIdx.x) * 32 + k] = v;
   }
 }
 
@@ -317,8 +328,12 @@ hipError_t ptc_weight_grad(const Geom& g, Links<float> L, Field<SX> x, int c_in,
                            int n_pairs, double* part, double* grad, hipStream_t st) {
   const int nblk = (2 * g.vh + 255) / 256;
   const int n_idx = PTC_PATHS * c_in * c_out;
-  hipLaunchKernelGGL((ptc_wgrad_kernel<SX>), dim3(nblk, n_idx), dim3(256), 0, st, g, L, x, c_in, gf, c_out, n_pairs,
-                     part);
+  if (c_out % 4 == 0)
+    hipLaunchKernelGGL((ptc_wgrad_kernel<SX, 4>), dim3(nblk, PTC_PATHS * c_in, c_out / 4), dim3(256), 0, st, g, L, x,
+                       c_in, gf, c_out, n_pairs, part);
+  else
+    hipLaunchKernelGGL((ptc_wgrad_kernel<SX, 1>), dim3(nblk, PTC_PATHS * c_in, c_out), dim3(256), 0, st, g, L, x,
+                       c_in, gf, c_out, n_pairs, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int waves = n_idx * 32;
