@@ -8,8 +8,10 @@ to X and Y, the summed force and the action.  All inputs are synthetic and
 resident in device memory before the timed region.
 
 Prints one JSON line.  Extra keys: the same solve in plain FP64 CG on the same
-GPU, the FP16 path, the error of each against the FP64 path, and the fused
-half-dslash bandwidth on a lattice far larger than the 256 MB Infinity Cache.
+GPU, the FP16 path and block CG, the error of every result against the FP64
+oracle (solutions, X, Y, force), the fused half-dslash bandwidth and GFLOP/s
+on lattices far larger than the 256 MB Infinity Cache, and the comparison
+rows (16^3x16 FP16 storage, the learned preconditioner, the 64-lattice batch).
 """
 from __future__ import annotations
 
@@ -26,6 +28,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "5-RHS D†D solve time to 1e-10 vs plain FP64 CG; dslash HBM GB/s, % peak"
 HBM_PEAK_GBS = 8000.0
+HOP_FLOP = 1320  # flop of the Wilson hopping term per output site per RHS
+
+
+def rel_err(a, b, np):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_config1(p, u, phi, np):
+    """The oracle's results for the bench workload (untimed): Alg. 2 (X, Y by
+    two per-RHS FP64 CG solves to 1e-13, the literal force) and the normal
+    equation solution (D^+D)^-1 Phi the solve rows compute."""
+    from oracle import force as fmod
+    from oracle import native, solvers
+    from oracle.dirac import WilsonDirac
+    d = native.NativeWilson(p.dims, p.bc, p.kappa, u)
+    x, _ = solvers.solve_D(d, phi, 1e-13)
+    y, _ = solvers.solve_Ddag(d, x, 1e-13)
+    g = fmod.coefficients_to_matrix(fmod.force_coefficients(WilsonDirac(p.dims, p.bc, p.kappa, u), x, y))
+    z, _ = solvers.cg_normal(d, phi, 1e-13)
+    return {"x": x, "y": y, "g": g, "s": fmod.action(None, x), "z": z}
+
+
+def oracle_first_rhs(p, u, b, tol=1e-12):
+    """The oracle's (D^+D)^-1 b for the first RHS only (16^3x16 rows: one FP64
+    CG with the compiled operator, untimed)."""
+    from oracle import native, solvers
+    d = native.NativeWilson(p.dims, p.bc, p.kappa, u)
+    x, _ = solvers.cg(d.DdagD, b[:1], tol)
+    return x
 
 
 COUNTERS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -155,6 +186,10 @@ def main():
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+    # the same step once more (untimed), keeping X and Y for the oracle comparison
+    g_step, action_step, stats_step, _, x_step, y_step = lat.force(phi, params=params, want_xy=True)
+    print("[bench] oracle reference for the bench workload", file=sys.stderr, flush=True)
+    ref = oracle_config1(p, u, phi_h, np)
 
     # dominant kernel: the fused hopping kernel with the D epilogue of the inner
     # CG (both parities in one launch), same launch shape as in the solve,
@@ -168,6 +203,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.prec, n, shape),
                 "kernel": kernel_name(args.prec, shape), "launch_us": round(hop_ms * 1e3, 3),
+                "timing": "HIP events around 200 back-to-back launches on a nonzero field, solver launch shape",
+                "residency": "cache-resident: %.1f MB per launch, inside the 256 MB Infinity Cache; "
+                             "launch-latency bound (see roofline_hbm_lattice for the HBM-resident figure)"
+                             % (per_launch / 1e6),
+                "gflops": round(HOP_FLOP * vd * n / (hop_ms * 1e-3) / 1e9, 1),
                 "shape": list(shape),
                 "algorithmic_bytes_per_launch": int(per_launch)}
 
@@ -188,6 +228,7 @@ def main():
     sb_ms, xb, stb = solve_ms("fp64", precond="blockcg")  # one Krylov space for all RHS
     x64h = x64.cpu().numpy()
     err = lambda a: float(np.linalg.norm(a.cpu().numpy() - x64h) / np.linalg.norm(x64h))
+    err_o = lambda a: rel_err(a.cpu().numpy(), ref["z"], np)
 
     out = {
         "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms", "n_gpus": 1,
@@ -205,50 +246,113 @@ def main():
         "iters": {args.prec: [s["iters"] for s in st_this], "fp64": [s["iters"] for s in st64],
                   "fp16": [s["iters"] for s in st16], "block_cg_fp64": [s["iters"] for s in stb]},
         "solution_rel_err_vs_fp64_path": {args.prec: err(x_this), "fp16": err(x16), "block_cg_fp64": err(xb)},
+        "rel_err_vs_oracle": {
+            "step": {"force": rel_err(g_step.cpu().numpy(), ref["g"], np),
+                     "X": rel_err(x_step.cpu().numpy(), ref["x"], np),
+                     "Y": rel_err(y_step.cpu().numpy(), ref["y"], np),
+                     "action": float(max(abs(a - b) / b for a, b in zip(action_step, ref["s"])))},
+            "solve": {args.prec: err_o(x_this), "fp64": err_o(x64), "fp16": err_o(x16),
+                      "block_cg_fp64": err_o(xb)},
+            "oracle": "FP64 CPU oracle: per-RHS CG to 1e-13 (Alg. 2's two solves for X, Y; the normal "
+                      "equations for the solve rows), literal per-generator force"},
         "true_rel_resid_max": max(s["true_rel_resid"] for s in st_this),
     }
 
     if not args.no_bandwidth:
-        dims = tuple(int(v) for v in args.bw_dims.split(","))
-        print(f"[bench] bandwidth lattice {dims}", file=sys.stderr, flush=True)
-        big = bandwidth_lattice(dims, synth, mfq, torch, dev, np)
-        bw = {}
-        vdb = dims[0] * dims[1] * dims[2] * dims[3]
-        for prec in ("fp64", "fp32", "fp16"):
-            for nr in (1, 5):
-                ms = big.time_hop(prec, nr, iters=20)
-                gbs = hop_bytes_per_site_rhs(prec, nr) * vdb * nr / (ms * 1e-3) / 1e9
-                bw[f"{prec}_n{nr}"] = {"us": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
-                                       "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                       "shape": list(big.hop_shape(prec, nr))}
-                print(f"[bench] bw {prec} n={nr}: {gbs:.1f} GB/s", file=sys.stderr, flush=True)
-        out["dslash_bandwidth"] = {"dims": list(dims), "bc": "periodic",
-                                   "kernel": "hop_kernel<EPI_D>", "runs": bw}
-        big.close()
-        torch.cuda.empty_cache()
+        out["dslash_bandwidth"] = bandwidth_runs(args, synth, mfq, torch, dev, np)
+        main_run = out["dslash_bandwidth"].get("32x32x32x64_periodic", {}).get("runs", {}).get("fp32_n5")
+        if main_run:
+            out["roofline_hbm_lattice"] = {
+                "bound": "hbm", "achieved": main_run["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": main_run["frac"], "gflops": main_run["GFLOP/s"], "launch_us": main_run["us"],
+                "kernel": "inner-solver hopping kernel, D epilogue, FP32, 5 RHS, both parities",
+                "workload": "32^3x64 periodic, 5 RHS (HBM-resident: 2.4 GB per launch)",
+                "shape": main_run["shape"]}
 
     if not args.no_rows:
         out["rows"] = run_rows(args, synth, mfq, torch, dev, np)
 
     if not args.no_cpu_baseline:
-        from oracle import force as fmod
-        from oracle import native
-
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        d = native.NativeWilson(p.dims, p.bc, p.kappa, u)
-        print(f"[bench] cpu oracle: one full step, {threads} threads", file=sys.stderr, flush=True)
-        t = time.perf_counter()
-        from oracle import solvers
-        x, _ = solvers.solve_D(d, phi_h, 1e-10)
-        y, _ = solvers.solve_Ddag(d, x, 1e-10)
-        from oracle.dirac import WilsonDirac
-        fmod.force_coefficients(WilsonDirac(p.dims, p.bc, p.kappa, u), x, y)
-        cpu_ms = (time.perf_counter() - t) * 1e3
-        out["cpu_baseline"] = {"value": round(cpu_ms, 2), "unit": "ms", "cores": threads, "kind": "oracle",
-                               "sample": "one full step of the same workload: Alg. 2 with two per-RHS "
-                                         "FP64 CG solves (normal equations, tol 1e-10) and the force"}
+        out["cpu_baseline"] = cpu_baseline(p, u, phi_h, np)
     lat.close()
     print(json.dumps(out))
+
+
+def cpu_baseline(p, u, phi_h, np):
+    """The oracle as it stands, timed on the host: Alg. 2 for the bench
+    workload (two per-RHS FP64 CG solves to 1e-10 with the compiled operator,
+    then the literal force), median of 3 on all cores; then a bounded sample
+    on one core (the first pseudo-fermion only, scaled by the RHS count)."""
+    from oracle import force as fmod
+    from oracle import native, solvers
+    from oracle.dirac import WilsonDirac
+
+    d = native.NativeWilson(p.dims, p.bc, p.kappa, u)
+    wd = WilsonDirac(p.dims, p.bc, p.kappa, u)
+
+    def alg2(phi):
+        t = time.perf_counter()
+        x, _ = solvers.solve_D(d, phi, 1e-10)
+        y, _ = solvers.solve_Ddag(d, x, 1e-10)
+        fmod.force_coefficients(wd, x, y)
+        return (time.perf_counter() - t) * 1e3
+
+    threads = native.set_threads(0)
+    print(f"[bench] cpu oracle: one full step x3, {threads} threads", file=sys.stderr, flush=True)
+    runs = sorted(alg2(phi_h) for _ in range(3))
+    one_cg = time.perf_counter()
+    solvers.cg_normal(d, phi_h, 1e-10)
+    one_cg = (time.perf_counter() - one_cg) * 1e3
+    native.set_threads(1)
+    print("[bench] cpu oracle: first pseudo-fermion, 1 thread", file=sys.stderr, flush=True)
+    single = alg2(phi_h[:1]) * phi_h.shape[0]
+    native.set_threads(threads)
+    return {"value": round(runs[1], 2), "unit": "ms", "cores": threads, "kind": "oracle",
+            "runs_ms": [round(v, 2) for v in runs],
+            "sample": "one full step of the same workload, median of 3: Alg. 2 as the oracle states it "
+                      "(two per-RHS FP64 CG solves on the normal equations, tol 1e-10, compiled operator "
+                      "with OpenMP over sites; then the literal per-generator force)",
+            "one_core": {"value": round(single, 2), "unit": "ms", "cores": 1,
+                         "sample": "the first pseudo-fermion's Alg. 2 on one thread, times the 5 RHS"},
+            "one_cg_normal_ms": round(one_cg, 2),
+            "one_cg_normal_note": "the oracle's single CG on D^+D for all 5 RHS (the solve the GPU step "
+                                  "runs once), all cores"}
+
+
+BANDWIDTH_RUNS = (
+    # (dims, bc, precisions, RHS counts)
+    ((32, 32, 32, 64), "periodic", ("fp64", "fp32", "fp16"), (1, 5, 8)),
+    ((48, 48, 48, 48), "periodic", ("fp32",), (1, 5)),
+    ((32, 32, 32, 64), "sf", ("fp32",), (5,)),
+)
+
+
+def bandwidth_runs(args, synth, mfq, torch, dev, np):
+    """The inner solver's hopping kernel (D epilogue, both parities, tuned
+    launch shape) on lattices far larger than the 256 MB Infinity Cache:
+    algorithmic GB/s, fraction of the 8 TB/s HBM peak and GFLOP/s."""
+    out = {}
+    for dims, bc, precs, nrs in BANDWIDTH_RUNS:
+        if args.bw_dims != "32,32,32,64" and dims != tuple(int(v) for v in args.bw_dims.split(",")):
+            continue
+        print(f"[bench] bandwidth lattice {dims} {bc}", file=sys.stderr, flush=True)
+        big = bandwidth_lattice(dims, synth, mfq, torch, dev, np, bc=bc)
+        vd = dims[0] * dims[1] * dims[2] * (dims[3] - 1 if bc == "sf" else dims[3])
+        runs = {}
+        for prec in precs:
+            for nr in nrs:
+                ms = big.time_hop(prec, nr, iters=20)
+                gbs = hop_bytes_per_site_rhs(prec, nr) * vd * nr / (ms * 1e-3) / 1e9
+                runs[f"{prec}_n{nr}"] = {"us": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
+                                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                         "GFLOP/s": round(HOP_FLOP * vd * nr / (ms * 1e-3) / 1e9, 1),
+                                         "shape": list(big.hop_shape(prec, nr))}
+                print(f"[bench] bw {prec} n={nr}: {gbs:.1f} GB/s", file=sys.stderr, flush=True)
+        out["x".join(map(str, dims)) + "_" + bc] = {"dims": list(dims), "bc": bc, "runs": runs,
+                                                   "kernel": "hop kernel, D epilogue, both parities"}
+        big.close()
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_rows(args, synth, mfq, torch, dev, np):
@@ -293,6 +397,10 @@ def bench_fp16(synth, mfq, torch, dev, np):
                      "true_rel_resid_max": max(s["true_rel_resid"] for s in st)}
     for prec in ("fp32", "fp16"):
         res[prec]["rel_err_vs_fp64_path"] = float(np.linalg.norm(xs[prec] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+    print("[bench] row fp16: oracle CG for the first RHS", file=sys.stderr, flush=True)
+    x_or = oracle_first_rhs(p, p.links(), p.rhs())
+    for prec in ("fp64", "fp32", "fp16"):
+        res[prec]["rel_err_vs_oracle_rhs0"] = rel_err(xs[prec][:1], x_or, np)
     # block CG: the 5 RHS share one Krylov space (FP64)
     pr = mfq.make_params(tol=1e-10, prec="fp64", precond="blockcg", max_iter=50000)
     ms, (x, st, rc) = _timed(lambda: lat.solve(b, params=pr))
@@ -300,6 +408,7 @@ def bench_fp16(synth, mfq, torch, dev, np):
                             "true_rel_resid_max": max(s["true_rel_resid"] for s in st),
                             "rel_err_vs_fp64_path": float(np.linalg.norm(x.cpu().numpy() - xs["fp64"])
                                                           / np.linalg.norm(xs["fp64"])),
+                            "rel_err_vs_oracle_rhs0": rel_err(x.cpu().numpy()[:1], x_or, np),
                             "iteration_ratio_vs_fp64_cg": round(st[0]["iters"] / max(res["fp64"]["iters"]), 3)}
     lat.close()
     return res
@@ -339,9 +448,15 @@ def bench_learned(synth, mfq, torch, dev, np):
     ref = xs["cg_fp64"]
     for name in ("fgmres_identity", "fgmres_ptc"):
         res[name]["rel_err_vs_cg"] = float(np.linalg.norm(xs[name] - ref) / np.linalg.norm(ref))
+    print("[bench] row learned: oracle CG for the first RHS", file=sys.stderr, flush=True)
+    x_or = oracle_first_rhs(p, p.links(), p.rhs())
+    for name in ("cg_fp64", "fgmres_identity", "fgmres_ptc"):
+        res[name]["rel_err_vs_oracle_rhs0"] = rel_err(xs[name][:1], x_or, np)
     res["ptc_iteration_gain_vs_fgmres"] = round(sum(res["fgmres_identity"]["iters"]) /
                                                 max(1, sum(res["fgmres_ptc"]["iters"])), 3)
-    res["ptc_time_vs_cg"] = round(res["cg_fp64"]["ms"] / res["fgmres_ptc"]["ms"], 3)
+    # time ratios against plain FP64 CG (> 1: slower than CG)
+    res["ptc_ms_over_cg_ms"] = round(res["fgmres_ptc"]["ms"] / res["cg_fp64"]["ms"], 3)
+    res["identity_ms_over_cg_ms"] = round(res["fgmres_identity"]["ms"] / res["cg_fp64"]["ms"], 3)
     lat.close()
     return res
 
@@ -387,23 +502,28 @@ def bench_batch(synth, mfq, torch, dev, np):
     return res
 
 
-def bandwidth_links(dims, synth, np):
-    """Links of the bandwidth lattice (periodic): random SU(3) links on a
-    16^3 x 8 block, tiled over the lattice (the values do not matter for
-    bandwidth and numpy's 3x3 eigh is slow)."""
+def bandwidth_links(dims, synth, np, bc="periodic"):
+    """Links of a bandwidth lattice: random SU(3) links on a 16^3 x 8 block,
+    tiled over the lattice (the values do not matter for bandwidth and
+    numpy's 3x3 eigh is slow); an SF lattice gets one more time slice (its
+    T + 1 stored slices), the boundary slices holding tiled random links too
+    (they never enter D)."""
     blk = (min(16, dims[0]), min(16, dims[1]), min(16, dims[2]), min(8, dims[3]))
     ub = synth.random_links(blk, "periodic", 0.3, 7)
     reps = (1, dims[3] // blk[3], dims[2] // blk[2], dims[1] // blk[1], dims[0] // blk[0], 1, 1)
-    return np.ascontiguousarray(np.tile(ub, reps))
+    u = np.tile(ub, reps)
+    if bc == "sf":
+        u = np.concatenate([u, u[:, :1]], axis=1)
+    return np.ascontiguousarray(u)
 
 
 BANDWIDTH_KAPPA = 0.12
 
 
-def bandwidth_lattice(dims, synth, mfq, torch, dev, np):
-    """The bandwidth lattice as a library handle."""
-    ub = bandwidth_links(dims, synth, np)
-    return mfq.Lattice(dims, "periodic", BANDWIDTH_KAPPA, torch.from_numpy(ub).to(dev))
+def bandwidth_lattice(dims, synth, mfq, torch, dev, np, bc="periodic"):
+    """A bandwidth lattice as a library handle."""
+    ub = bandwidth_links(dims, synth, np, bc)
+    return mfq.Lattice(dims, bc, BANDWIDTH_KAPPA, torch.from_numpy(ub).to(dev))
 
 
 def profile_kernels(args, synth, mfq, torch, dev, np):

@@ -209,7 +209,9 @@ void mfq_batch_destroy(mfq_batch* batch);
 /* Random initial weights (identity path near 1/sqrt(8) in both layers). */
 int mfq_precond_init(mfq_handle* h, unsigned long long seed, double scale);
 int mfq_precond_set_weights(mfq_handle* h, const double* w_host);
-/* which = 0: FP32 master weights, 1: BF16-rounded inference weights. */
+/* which = 0: FP32 master weights, 1: BF16-rounded inference weights,
+ * 2 / 3: Adam's first / second moment estimates (same layout: the real part
+ * holds the moment of Re W, the imaginary part that of Im W). */
 int mfq_precond_get_weights(mfq_handle* h, int which, double* w_host);
 /* out = M in for n_rhs canonical spinors (inference weights). */
 int mfq_precond_apply(mfq_handle* h, const double* in_dev, double* out_dev, int n_rhs, void* stream);
@@ -238,8 +240,9 @@ int mfq_precond_load(mfq_handle* h, const char* path);
 const char* mfq_last_error(void);
 
 /* Average device time (ms) of one launch of the dominant solver kernel (the
- * fused half-dslash of the inner CG at precision `prec` for n_rhs RHS), timed
- * with HIP events around `iters` back-to-back launches on `stream`. */
+ * fused half-dslash of the inner CG at precision `prec` for n_rhs RHS, both
+ * parities, in the solver's launch shape), timed with HIP events around
+ * `iters` back-to-back launches on `stream`, on a fixed nonzero field. */
 int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, double* ms_out);
 
 /* Launch-shape autotuning of the inner solver's hopping kernel (on by

@@ -39,8 +39,20 @@ def _load():
         lib.wilson_ref_hop.restype = None
         lib.wilson_ref_gamma.argtypes = [i, p]
         lib.wilson_ref_gamma.restype = None
+        lib.wilson_ref_set_threads.argtypes = [i]
+        lib.wilson_ref_set_threads.restype = None
+        lib.wilson_ref_get_threads.argtypes = []
+        lib.wilson_ref_get_threads.restype = i
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the compiled operator (n <= 0: OpenMP's default);
+    returns the count now in force."""
+    lib = _load()
+    lib.wilson_ref_set_threads(int(n))
+    return int(lib.wilson_ref_get_threads())
 
 
 def gamma(mu: int) -> np.ndarray:

@@ -106,3 +106,11 @@ void wilson_ref_hop(const cplx* U, const cplx* in, cplx* out, int lx, int ly, in
     }
   }
 }
+
+/* Thread count of the loops above (for timing the oracle on one core); 0 or
+ * less leaves OpenMP's default. */
+#include <omp.h>
+void wilson_ref_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+int wilson_ref_get_threads(void) { return omp_get_max_threads(); }

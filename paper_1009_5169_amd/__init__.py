@@ -207,8 +207,8 @@ def _precond_set_weights(self, w):
 def _precond_get_weights(self, which: str = "master"):
     import numpy as np
     out = np.zeros(N_PTC_COMPLEX, dtype=np.complex128)
-    _lib.check(_lib.lib().mfq_precond_get_weights(self._h, 0 if which == "master" else 1,
-                                                  ctypes.c_void_p(out.ctypes.data)))
+    code = {"master": 0, "inference": 1, "adam_m": 2, "adam_v": 3}[which]
+    _lib.check(_lib.lib().mfq_precond_get_weights(self._h, code, ctypes.c_void_p(out.ctypes.data)))
     return out
 
 

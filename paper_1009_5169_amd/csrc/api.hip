@@ -145,14 +145,9 @@ int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field
     case MFQ_OP_HOP_EO:
     case MFQ_OP_HOP_OE: {
       const int par = op == MFQ_OP_HOP_EO ? 0 : 1;
-      // zero the other parity of the output, then the one hopping launch
-      const size_t per_par = (size_t)Store<S>::NC * h->g.vs;
-      for (int r = 0; r < n_rhs; ++r)
-        HIPCHK(hipMemsetAsync(out.data + ((size_t)r * 2 + (1 - par)) * per_par, 0,
-                              per_par * sizeof(typename Store<S>::chunk), st));
-      if (sizeof(S) == 2)
-        for (int r = 0; r < n_rhs; ++r)
-          HIPCHK(hipMemsetAsync(out.norm + ((size_t)r * 2 + (1 - par)) * h->g.vs, 0, h->g.vs * sizeof(float), st));
+      // zero the other parity of the output (a fill kernel, no memset node
+      // for callers that capture), then the one hopping launch
+      HIPCHK(launch_zero_parity<S>(h->g, out, n_rhs, 1 - par, st));
       HIPCHK(run(EPI_HOP, in, out, par, 0, 1.0));
       return MFQ_OK;
     }
@@ -171,6 +166,11 @@ int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field
     default:
       return fail(MFQ_ERR_ARG, "unknown operator");
   }
+}
+
+int apply_op_fp64(mfq_handle* h, int op, Field<double> in, Field<double> tmp, Field<double> out, int n_rhs,
+                  Shape sh2, hipStream_t st) {
+  return apply_op<double>(h, op, links_d(h), in, tmp, out, n_rhs, sh2, st);
 }
 
 // ------------------------------------------------------------- autotuner
@@ -316,6 +316,15 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   const double tol2 = P->tol * P->tol;
   const double delta2 = delta * delta;
   const int nb_full = (2 * g.vh + sh.sb - 1) / sh.sb;
+  // the FP64 true-residual launches: the tuned FP64 shape if one is known,
+  // else the inner shape with the direction split dropped where its LDS
+  // partial sums would not fit at FP64 width
+  Shape sh64 = sh;
+  if (sizeof(S) != 8 && !(h->autotune && tune_cache_lookup(h, n, 8, &sh64))) {
+    sh64 = sh;
+    if (sh64.ds && (size_t)sh64.nr * (sh64.ds - 1) * 24 * 64 * sizeof(double) > 65536) sh64.ds = 0;
+  }
+  const int nb64 = hop_grid_x(g, sh64, 2);
   CgScalars* sc = (CgScalars*)w.sc.ptr;
   Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), r64 = w.r64.view(g), t64 = w.t64.view(g);
 
@@ -382,14 +391,14 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     a64.dagger = 0;
     a64.part = nullptr;
     a64.par = 2;
-    HIPCHK(launch_hop<double, double>(EPI_D, a64, sh, st));
+    HIPCHK(launch_hop<double, double>(EPI_D, a64, sh64, st));
     a64.in = a64.self = t64;
     a64.bvec = b64;
     a64.r64 = r64;
     a64.dagger = 1;
     a64.part = part_slot(h, 0);
-    HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh, st));
-    Partials pt{part_slot(h, 0), nb2};
+    HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh64, st));
+    Partials pt{part_slot(h, 0), nb64};
     HIPCHK(launch_finish(mode == UPD_ALL ? FIN_TRUE : FIN_TRUE_FLAGGED, &pt, 1, n, sc, nullptr, tol2, delta2, st));
     HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, sh, st));
     return MFQ_OK;
@@ -779,7 +788,8 @@ int mfq_time_hop(mfq_handle* h, int prec, int n_rhs, int iters, void* stream, do
     *ms_out = ms / iters;
     return MFQ_OK;
   };
-  HIPCHK(hipMemsetAsync(w.b64.data.ptr, 0, field_chunks<double>(g, n_rhs) * sizeof(d2), st));
+  // time on a nonzero field, as the solve's own fields are
+  HIPCHK(launch_fill_pattern(g, w.b64.view(g), n_rhs, sh0, st));
   Shape sh;
   if (prec == MFQ_PREC_FP64) {
     HIPCHK(w.pd.alloc(g, n_rhs));

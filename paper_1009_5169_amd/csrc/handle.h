@@ -90,6 +90,10 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
 int run_block_cg(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
 // the tuned launch shape of the FP64 hopping kernel for n RHS
 int fp64_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out);
+// out = op(in) in FP64 (mfq_op); tmp is scratch for DDAGD; sh2 is the shape of
+// the both-parity launches
+int apply_op_fp64(mfq_handle* h, int op, Field<double> in, Field<double> tmp, Field<double> out, int n_rhs,
+                  Shape sh2, hipStream_t st);
 // learned preconditioner (ptc_host.hip)
 void ptc_free(mfq_handle* h);
 int ptc_apply_fields(mfq_handle* h, Field<double> in, Field<double> out, int n, hipStream_t st);

@@ -542,6 +542,40 @@ __global__ void init_residual_kernel(Geom g, Field<double> b, Field<double> r64,
   block_partial(v, part, n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
 }
 
+// A fixed nonzero test field (for kernel timing): component c of site q of
+// RHS r holds a small integer hash mapped to [-0.5, 0.5).
+__global__ void fill_pattern_kernel(Geom g, Field<double> f, int n_rhs) {
+  MFQ_FULL_LANE
+  Spinor<double> a;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const unsigned hsh = (unsigned)(q * 2654435761u) ^ (unsigned)(r * 40503u + k * 977u);
+    a.v[k] = {(double)((hsh >> 8) & 1023) / 1024.0 - 0.5, (double)((hsh >> 18) & 1023) / 1024.0 - 0.5};
+  }
+  store_spinor(f, r, par, s, a);
+}
+
+template <typename S>
+__global__ void zero_parity_kernel(Geom g, Field<S> f, int n_rhs, int par) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (s >= g.vh || r >= n_rhs) return;
+  typename Store<S>::chunk z;
+  for (int k = 0; k < (int)(sizeof(z) / sizeof(z[0])); ++k) z[k] = 0;
+#pragma unroll
+  for (int c = 0; c < Store<S>::NC; ++c) f.data[f.cidx(r, par, c, s)] = z;
+  if constexpr (sizeof(S) == 2) f.norm[f.nidx(r, par, s)] = 0.f;
+}
+
+template <typename S>
+hipError_t launch_zero_parity(const Geom& g, Field<S> f, int n_rhs, int par, hipStream_t st) {
+  hipLaunchKernelGGL((zero_parity_kernel<S>), dim3((g.vh + 255) / 256, n_rhs), dim3(256), 0, st, g, f, n_rhs, par);
+  return hipGetLastError();
+}
+template hipError_t launch_zero_parity<double>(const Geom&, Field<double>, int, int, hipStream_t);
+template hipError_t launch_zero_parity<float>(const Geom&, Field<float>, int, int, hipStream_t);
+template hipError_t launch_zero_parity<_Float16>(const Geom&, Field<_Float16>, int, int, hipStream_t);
+
 static inline dim3 full_grid(const Geom& g, Shape sh, int n_rhs) {
   return dim3((2 * g.vh + sh.sb - 1) / sh.sb, (n_rhs + sh.nr - 1) / sh.nr);
 }
@@ -577,6 +611,10 @@ hipError_t launch_norm2(const Geom& g, Field<double> f, double* part, int n_rhs,
                         hipStream_t st) {
   (void)nblk;
   hipLaunchKernelGGL(norm2_kernel, full_grid(g, sh, n_rhs), dim3(sh.sb, sh.nr), 0, st, g, f, part, n_rhs);
+  return hipGetLastError();
+}
+hipError_t launch_fill_pattern(const Geom& g, Field<double> f, int n_rhs, Shape sh, hipStream_t st) {
+  hipLaunchKernelGGL(fill_pattern_kernel, full_grid(g, sh, n_rhs), dim3(sh.sb, sh.nr), 0, st, g, f, n_rhs);
   return hipGetLastError();
 }
 hipError_t launch_init_residual(const Geom& g, Field<double> b, Field<double> r64, double* part, int n_rhs,

@@ -137,6 +137,10 @@ hipError_t launch_convert(const Geom& g, Field<SA> src, Field<SB> dst, int gamma
                           Shape sh, hipStream_t st);
 hipError_t launch_norm2(const Geom& g, Field<double> f, double* part, int n_rhs, Shape sh,
                         int nblk, hipStream_t st);
+// zero parity `par` of every RHS of f (values and, for FP16, norms)
+template <typename S>
+hipError_t launch_zero_parity(const Geom& g, Field<S> f, int n_rhs, int par, hipStream_t st);
+hipError_t launch_fill_pattern(const Geom& g, Field<double> f, int n_rhs, Shape sh, hipStream_t st);
 hipError_t launch_init_residual(const Geom& g, Field<double> b, Field<double> r64, double* part,
                                 int n_rhs, Shape sh, hipStream_t st);
 

@@ -132,3 +132,61 @@ def test_fgmres_exact_inverse_converges_in_one_step_and_solves():
     want = np.linalg.solve(a, b.reshape(2, -1).T).T.reshape(b.shape)
     assert np.abs(x2 - want).max() < 1e-9 * np.abs(want).max()
     assert all(s.true_rel_resid <= 1e-12 for s in st2)
+
+
+# ---- Adam (Kingma and Ba, "Adam: A method for stochastic optimization",
+# Algorithm 1), each of Re and Im a real parameter of its own.
+
+def test_adam_first_step_is_lr_times_sign_per_real_part():
+    """From m = v = 0 the bias-corrected moments at t = 1 are g and g^2, so
+    every real parameter moves by lr g / (|g| + eps): lr sign(g) for |g| >> eps,
+    separately for Re and Im (a mixed-up Re/Im second moment would scale one
+    part by the other's magnitude)."""
+    g = np.array([3.0 - 0.002j, -0.5 + 7.0j, 1e-3 + 0j])
+    w = np.array([0.25 + 0.5j, -1.0 + 0.0j, 2.0 - 3.0j])
+    lr, eps = 0.01, 1e-8
+    w1, m1, v1 = ptc.adam_step(w, g, 0, 0, 1, lr=lr, eps=eps)
+    want = w - lr * (g.real / (np.abs(g.real) + eps) + 1j * g.imag / (np.abs(g.imag) + eps))
+    np.testing.assert_allclose(w1, want, rtol=0, atol=1e-15)
+    # 1e-3 is still >> eps: a full lr step (to 1e-5 of lr), even though |g|
+    # is 3000x smaller than the largest component
+    np.testing.assert_allclose((w - w1).real, lr * np.sign(g.real), atol=2e-5 * lr)
+    np.testing.assert_allclose((w - w1)[:2].imag, lr * np.sign(g.imag[:2]), atol=2e-5 * lr)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v1, 0.001 * (g.real ** 2 + 1j * g.imag ** 2), rtol=1e-15)
+
+
+def test_adam_two_steps_of_a_scalar_by_hand():
+    """w0 = 1, lr = 0.1, g1 = 1/2, g2 = -1/4 (beta = 0.9, 0.999), worked out by
+    hand in exact fractions: m1 = 1/20, v1 = 1/4000, so m^ = 1/2 and v^ = 1/4
+    and w1 = 1 - 0.1 (1/2) / (1/2 + eps) = 0.900000002;
+    m2 = 9/10 * 1/20 - 1/40 = 1/50, v2 = 999/1000 * 1/4000 + 1/16000
+    = 1249/4000000, m^ = (1/50) / (19/100) = 2/19,
+    v^ = (1249/4000000) / (1999/1000000) = 1249/7996, sqrt(v^) = 0.3952253807016642,
+    w2 = w1 - 0.1 (2/19) / (0.3952253807016642 + eps) = 0.8733662987078462."""
+    w, m, v = np.array([1.0 + 0j]), 0, 0
+    w, m, v = ptc.adam_step(w, np.array([0.5 + 0j]), m, v, 1, lr=0.1)
+    assert abs(m[0].real - 1 / 20) < 1e-15 and abs(v[0].real - 1 / 4000) < 1e-17
+    assert abs(w[0].real - 0.900000002) < 1e-15
+    w, m, v = ptc.adam_step(w, np.array([-0.25 + 0j]), m, v, 2, lr=0.1)
+    assert abs(m[0].real - 1 / 50) < 1e-15
+    assert abs(v[0].real - 1249 / 4000000) < 1e-17
+    assert abs(w[0].real - 0.8733662987078462) < 1e-14
+    assert w[0].imag == 0.0 and m[0].imag == 0.0 and v[0].imag == 0.0
+
+
+def test_adam_bias_correction_makes_constant_gradients_exact():
+    """With the same gradient every step, m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2 exactly, so the bias-corrected step is
+    lr g / (|g| + eps) at every t (a wrong power in the correction, e.g.
+    b^(t+1), shrinks the early steps)."""
+    g = np.array([0.3 - 2.0j, -4.0 + 0.01j])
+    w = np.zeros(2, dtype=complex)
+    m = v = 0
+    lr = 1e-3
+    for t in range(1, 8):
+        w_new, m, v = ptc.adam_step(w, g, m, v, t, lr=lr)
+        step = w - w_new
+        want = lr * (g.real / (np.abs(g.real) + 1e-8) + 1j * g.imag / (np.abs(g.imag) + 1e-8))
+        np.testing.assert_allclose(step, want, rtol=1e-9)
+        w = w_new
