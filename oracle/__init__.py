@@ -16,6 +16,9 @@ split), in numpy complex128:
 * ``force``   -- the pseudo-fermion action sum_i |D^-1 phi_i|^2 (Eq. 2) and the
                  MD force summed over pseudo-fermions (Eq. 3), written as the
                  literal derivative per su(3) generator.
+* ``schur``   -- the even/odd Schur complement D^ = 1 - kappa^2 H_eo H_oe,
+                 solves of D and D^+ through it, and the even/odd action
+                 variant S_eo = sum_i |D^-1 phi_i,e|^2 with its force.
 * ``hmc``     -- leapfrog molecular dynamics and Delta-H for the dt^2 pin.
 * ``ptc``     -- the gauge-covariant parallel-transport convolution network
                  used as a learned preconditioner, forward and adjoint.
