@@ -19,6 +19,10 @@ split), in numpy complex128:
 * ``schur``   -- the even/odd Schur complement D^ = 1 - kappa^2 H_eo H_oe,
                  solves of D and D^+ through it, and the even/odd action
                  variant S_eo = sum_i |D^-1 phi_i,e|^2 with its force.
+* ``bicgstab``-- the paper's solver family on D: per-RHS BiCGStab, the global
+                 (Gl-) and block (Bl-) BiCGStab of Sec. 3.1, each with an
+                 optional right preconditioner (the mixed-precision inner
+                 solve of Sec. 3.2).
 * ``hmc``     -- leapfrog molecular dynamics and Delta-H for the dt^2 pin.
 * ``ptc``     -- the gauge-covariant parallel-transport convolution network
                  used as a learned preconditioner, forward and adjoint.
