@@ -82,7 +82,11 @@ typedef enum { MFQ_PREC_FP64 = 0, MFQ_PREC_FP32_RELIABLE = 1, MFQ_PREC_FP16_REFI
  *   HOP_EO   out_even = H_eo in_odd,  out_odd = 0
  *   HOP_OE   out_odd  = H_oe in_even, out_even = 0
  *   HOP      out = H in     (both parities)      HOP_DAG  out = H^+ in
- *   D, DDAG, DDAGD          out = D in, D^+ in, D^+ D in                   */
+ *   D, DDAG, DDAGD          out = D in, D^+ in, D^+ D in
+ *   SCHUR, SCHUR_DAG, SCHUR_NORMAL   out_even = D^ in_even, D^^+ in_even,
+ *            D^^+ D^ in_even with D^ = 1 - kappa^2 H_eo H_oe, the Schur
+ *            complement of the even/odd blocks of D (the site even/odd
+ *            preconditioning of Sec. 3.1); out_odd = 0, in_odd is ignored  */
 typedef enum {
   MFQ_OP_HOP_EO = 0,
   MFQ_OP_HOP_OE = 1,
@@ -90,8 +94,23 @@ typedef enum {
   MFQ_OP_DDAG = 3,
   MFQ_OP_DDAGD = 4,
   MFQ_OP_HOP = 5,
-  MFQ_OP_HOP_DAG = 6
+  MFQ_OP_HOP_DAG = 6,
+  MFQ_OP_SCHUR = 7,
+  MFQ_OP_SCHUR_DAG = 8,
+  MFQ_OP_SCHUR_NORMAL = 9
 } mfq_op;
+
+/* Solve route for CG (precond MFQ_PC_NONE):
+ *   FULL   CG on the normal operator D^+D over every site (x = (D^+D)^-1 b;
+ *          the force takes one such solve: Z = (D^+D)^-1 g5 Phi).
+ *   SCHUR  even/odd preconditioned: every solve of D (or D^+) runs CG on
+ *          D^^+ D^ over the even sites (half the volume, better conditioned)
+ *          and rebuilds the odd sites; (D^+D)^-1 b then takes two of them
+ *          (D^+ w = b, D x = w) and the force too (D X = Phi, D^+ Y = X).
+ *          tol applies to each Schur solve's own normal equations; the
+ *          statistics report the summed iterations and the final FP64
+ *          residual of the full system. */
+typedef enum { MFQ_ROUTE_FULL = 0, MFQ_ROUTE_SCHUR = 1 } mfq_route;
 
 /* Solver selection: NONE is CG on D^+D; PTC is restarted flexible GMRES
  * (restart = mfq_solve_params.restart, FP64 Arnoldi) right-preconditioned by
@@ -105,7 +124,29 @@ typedef enum {
  * Gram matrices and solves in FP64; it restarts from the FP64 true residual
  * if the recursive residual drifted, and hands the remaining residual to
  * batched CG (status MFQ_FELL_BACK) if an n x n solve breaks down. */
-typedef enum { MFQ_PC_NONE = 0, MFQ_PC_PTC = 1, MFQ_PC_IDENTITY = 2, MFQ_PC_BLOCKCG = 3 } mfq_pc;
+typedef enum {
+  MFQ_PC_NONE = 0,
+  MFQ_PC_PTC = 1,
+  MFQ_PC_IDENTITY = 2,
+  MFQ_PC_BLOCKCG = 3,
+  MFQ_PC_BICGSTAB = 4,
+  MFQ_PC_GL_BICGSTAB = 5,
+  MFQ_PC_BL_BICGSTAB = 6
+} mfq_pc;
+/* The paper's own solvers (Sec. 3.1-3.2), selected by BICGSTAB (BiCGStab
+ * per RHS, the sequential baseline), GL_BICGSTAB (Global BiCGStab: Frobenius
+ * inner products over the block) and BL_BICGSTAB (Block BiCGStab: n x n
+ * alpha and beta from the shadow block), n_rhs <= 8: they solve D (and D^+)
+ * itself, not the normal equations, through the even/odd Schur complement
+ * D^ = 1 - kappa^2 H_eo H_oe (odd sites rebuilt).  prec FP64: FP64
+ * throughout; FP32_RELIABLE: FP64 outer iteration whose right preconditioner
+ * is an FP32 BiCGStab solve per RHS to the relative tolerance inner_tol (at
+ * most inner_max_iter iterations), the mixed-precision preconditioning of
+ * Sec. 3.2; FP16 is refused.  The outer iteration stops on the FP64 true
+ * residual |b_e - D^ x_e| <= tol |b_e| of the even system, restarting from
+ * it (new shadow block) when the recursion lied or broke down (at most 5
+ * restarts).  (D^+D)^-1 b takes two such solves (D^+ w = b, D x = w), the
+ * force the two of Alg. 2 (D X = Phi, D^+ Y = X), mfq_solve_dirac one. */
 
 typedef struct {
   int dims[4]; /* Lx, Ly, Lz, T: even, >= 2 (T >= 4 for SF)                  */
@@ -122,6 +163,10 @@ typedef struct {
   int restart;           /* FGMRES restart length (PTC / IDENTITY; <= 0: 16)  */
   int check_every;       /* iterations between host polls (<= 0: default)    */
   int use_graph;         /* capture the inner iterations in a hipGraph        */
+  int route;             /* mfq_route (SCHUR needs precond MFQ_PC_NONE)       */
+  double inner_tol;      /* BiCGStab solvers, prec FP32_RELIABLE: relative
+                            tolerance of the inner FP32 solves (<= 0: 1e-4) */
+  int inner_max_iter;    /* ... and their iteration cap (<= 0: 500)          */
 } mfq_solve_params;
 
 typedef struct {
@@ -130,6 +175,9 @@ typedef struct {
   double true_rel_resid; /* final FP64 |b - A x| / |b|                        */
   double seconds;        /* wall time of the whole call                      */
   int status;            /* mfq_status of this RHS                            */
+  int inner_iters;       /* BiCGStab with FP32 inner solves: inner iterations,
+                            summed over the inner calls (else 0)             */
+  int inner_calls;       /* ... and the number of inner calls                */
 } mfq_solve_stats;
 
 /* Create a handle for one lattice and pack the links (canonical FP64 device
@@ -153,18 +201,95 @@ int mfq_dslash_prec(mfq_handle* h, int op, int prec, const double* in_dev, doubl
                     void* stream);
 
 /* x_i = (D^+ D)^-1 b_i for i < n_rhs, all RHS in one batched CG (Section 3.1:
- * the blocked form of the linear equations).  stats_host: n_rhs records. */
+ * the blocked form of the linear equations); with params->route = SCHUR as
+ * two even/odd-preconditioned solves (D^+ w = b, then D x = w).
+ * stats_host: n_rhs records. */
 int mfq_solve_multi_rhs(mfq_handle* h, const double* b_dev, double* x_dev, int n_rhs,
                         const mfq_solve_params* params, mfq_solve_stats* stats_host, void* stream);
 
+/* x_i = D^-1 b_i (dagger 0) or (D^+)^-1 b_i (dagger 1): one line of Alg. 2
+ * (its second line is D X = Phi, its third D^+ Y = X), through the even/odd
+ * Schur complement: with precond NONE by CG on D^^+ D^ (route SCHUR), with
+ * the BiCGStab selections by the paper's solvers.  Other selections return
+ * MFQ_ERR_ARG.  stats_host: n_rhs records (true_rel_resid: of the even
+ * system). */
+int mfq_solve_dirac(mfq_handle* h, int dagger, const double* b_dev, double* x_dev, int n_rhs,
+                    const mfq_solve_params* params, mfq_solve_stats* stats_host, void* stream);
+
 /* Alg. 2 for n_rhs pseudo-fermions: one batched normal-equation solve
  * Z = (D^+ D)^-1 g5 Phi gives Y = (D^+)^-1 D^-1 Phi = g5 Z and X = D^-1 Phi =
- * D^+ Y; then force_dev (links shape) = sum_i f[x_i, y_i] (Eq. 3) and
- * action_host[i] = |x_i|^2 (Eq. 2).  x_dev / y_dev may be NULL; if given they
- * receive X and Y (spinor shape). */
+ * D^+ Y (route FULL), or the two solves of Alg. 2 themselves, D X = Phi and
+ * D^+ Y = X, each through the even/odd Schur complement (route SCHUR); then
+ * force_dev (links shape) = sum_i f[x_i, y_i] (Eq. 3) and action_host[i] =
+ * |x_i|^2 (Eq. 2).  x_dev / y_dev may be NULL; if given they receive X and Y
+ * (spinor shape).  The statistics of route SCHUR sum both solves'
+ * iterations; true_rel_resid is that of the last solve's normal equations. */
 int mfq_fermion_force(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq_solve_params* params,
                       double* force_dev, double* action_host, double* x_dev, double* y_dev,
                       mfq_solve_stats* stats_host, void* stream);
+
+/* The even/odd-preconditioned action variant S = sum_i |D^-1 phi_i,e|^2
+ * (phi on the even sites; the odd sites of phi_dev are ignored), the form an
+ * HMC with even/odd preconditioning integrates (Sec. 3.1).  One CG on
+ * D^^+ D^ over the even sites gives Y_e = g5 (D^^+ D^)^-1 g5 phi_e and
+ * X_e = D^^+ Y_e = D^-1 phi_e; with X_o = kappa H_oe X_e and
+ * Y_o = kappa (H^+)_oe Y_e the force of this action is the Eq. 3 force of the
+ * full-lattice X and Y, so force_dev is filled as by mfq_fermion_force;
+ * action_host[i] = |X_e,i|^2.  x_dev / y_dev (may be NULL) receive the full X
+ * and Y.  params->route is ignored (always the even-site CG). */
+int mfq_fermion_force_eo(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq_solve_params* params,
+                         double* force_dev, double* action_host, double* x_dev, double* y_dev,
+                         mfq_solve_stats* stats_host, void* stream);
+
+/* ---- molecular dynamics: the HMC of Sec. 2 on the GPU -------------------
+ * Momenta use the force's layout: per link the Hermitian traceless
+ * P_mu(n) = sum_a P^a T^a (canonical links shape, FP64).  Equations of
+ * motion dU/dt = i P U, dP/dt = -G with G from mfq_fermion_force; the
+ * Hamiltonian H = 1/2 sum P^a P^a + sum_i |D^-1 phi_i|^2 (pseudo-fermion
+ * action only; the gauge action is not part of this library).  Only links
+ * that enter D move; the others (SF: spatial links at x0 = 0 and T, temporal
+ * links at x0 = 0, T-1, T) keep their values, and their momenta are ignored. */
+
+/* out_host = 1/2 sum_a P^a P^a = sum over entering links of Tr P^2 (FP64,
+ * fixed-order reduction on the device).  Host-blocking. */
+int mfq_kinetic_energy(mfq_handle* h, const double* mom_dev, double* out_host, void* stream);
+
+/* mom_dev <- mom_dev - eps * force_dev on the entering links.  Asynchronous. */
+int mfq_md_momenta(mfq_handle* h, const double* force_dev, double* mom_dev, double eps, void* stream);
+
+/* links_dev <- exp(i eps P) links_dev on the entering links (3x3 exponential
+ * in FP64: scaling and squaring of a degree-12 Taylor polynomial), then the
+ * handle's packed copies are refreshed (as mfq_update_links).  Host-blocking. */
+int mfq_md_links(mfq_handle* h, const double* mom_dev, double* links_dev, double eps, void* stream);
+
+typedef struct {
+  double tau;          /* trajectory length (> 0)                               */
+  int n_steps;         /* leapfrog steps (>= 1), dt = tau / n_steps             */
+  double rand_uniform; /* the Metropolis draw in [0, 1), supplied by the caller  */
+} mfq_hmc_params;
+
+typedef struct {
+  double delta_h;                  /* H_new - H_old, FP64                       */
+  double kinetic_old, kinetic_new; /* 1/2 sum P^a P^a                           */
+  double action_old, action_new;   /* sum_i |D^-1 phi_i|^2                      */
+  int accepted;                    /* 1 if rand_uniform < exp(-delta_h), i.e.
+                                      log(rand_uniform) < -delta_h            */
+  int force_evals;                 /* n_steps + 1                               */
+  int solver_iters;                /* summed over force evaluations and RHS      */
+  double seconds;
+} mfq_hmc_result;
+
+/* One HMC trajectory with the leapfrog integrator (P -= dt/2 G; then n_steps
+ * times U <- exp(i dt P) U, G(U), P -= dt G, the last kick dt/2), every force
+ * from mfq_fermion_force with `sp` (so route, precision and solver are the
+ * caller's choice), Delta H in FP64 and the Metropolis decision with the
+ * caller's draw.  On acceptance links_dev / mom_dev hold the new U and P; on
+ * rejection they are restored to their values on entry (and the handle's
+ * packed links with them).  phi_dev: n_rhs canonical pseudo-fermions, fixed
+ * during the trajectory.  Returns the worst solver status (MFQ_OK,
+ * MFQ_NOT_CONVERGED, MFQ_FELL_BACK) or a negative error.  Host-blocking. */
+int mfq_hmc_trajectory(mfq_handle* h, double* links_dev, double* mom_dev, const double* phi_dev, int n_rhs,
+                       const mfq_hmc_params* hp, const mfq_solve_params* sp, mfq_hmc_result* out, void* stream);
 
 /* ---- many lattices in one persistent launch per CG phase --------------
  * A batch groups distinct handles (lattices of any size, each with its own

@@ -83,7 +83,8 @@ class Lattice:
         Keyword arguments go to make_params: tol, max_iter, prec ("fp64", "fp32",
         "fp16"), reliable_delta, precond ("none": batched CG; "blockcg": block CG,
         FP64, at most 8 RHS; "ptc" / "identity": FGMRES with / without the learned
-        preconditioner), restart, check_every, use_graph."""
+        preconditioner), restart, check_every, use_graph, route ("full": CG on
+        D^+D; "schur": two even/odd-preconditioned solves)."""
         n = self._check_spinor(b)
         p = params if params is not None else make_params(**kw)
         x = torch.empty_like(b)
@@ -93,8 +94,24 @@ class Lattice:
         _lib.check(rc, allow=(0, 1, 2))
         return x, [s.as_dict() for s in stats], rc
 
-    def force(self, phi: torch.Tensor, params=None, want_xy: bool = False, stream=None, **kw):
-        """Alg. 2: returns (G, action[n], stats, status[, X, Y])."""
+    def solve_dirac(self, b: torch.Tensor, dagger: bool = False, params=None, stream=None, **kw):
+        """x = D^-1 b (or (D^+)^-1 b) through the even/odd Schur complement: CG
+        on the even normal equations (precond "none") or the paper's BiCGStab
+        solvers (precond "bicgstab", "gl_bicgstab", "bl_bicgstab"; prec "fp32"
+        adds the FP32 inner solve as preconditioner).  Returns (x, stats, status)."""
+        n = self._check_spinor(b)
+        p = params if params is not None else make_params(**kw)
+        x = torch.empty_like(b)
+        stats = (SolveStats * n)()
+        rc = _lib.lib().mfq_solve_dirac(self._h, int(bool(dagger)), _lib.dptr(b), _lib.dptr(x), n, ctypes.byref(p),
+                                        stats, _lib.stream_ptr(stream))
+        _lib.check(rc, allow=(0, 1, 2))
+        return x, [s.as_dict() for s in stats], rc
+
+    def force(self, phi: torch.Tensor, params=None, want_xy: bool = False, stream=None, eo_action=False, **kw):
+        """Alg. 2: returns (G, action[n], stats, status[, X, Y]).  route="schur"
+        runs its two solves through the even/odd Schur complement; eo_action=True
+        evaluates the even/odd-preconditioned action |D^-1 phi_e|^2 instead."""
         n = self._check_spinor(phi)
         p = params if params is not None else make_params(**kw)
         g = torch.empty(link_shape(self.dims, self.bc), dtype=torch.complex128, device=phi.device)
@@ -102,13 +119,58 @@ class Lattice:
         stats = (SolveStats * n)()
         x = torch.empty_like(phi) if want_xy else None
         y = torch.empty_like(phi) if want_xy else None
-        rc = _lib.lib().mfq_fermion_force(
+        fn = _lib.lib().mfq_fermion_force_eo if eo_action else _lib.lib().mfq_fermion_force
+        rc = fn(
             self._h, _lib.dptr(phi), n, ctypes.byref(p), _lib.dptr(g), action,
             _lib.dptr(x) if want_xy else None, _lib.dptr(y) if want_xy else None, stats,
             _lib.stream_ptr(stream))
         _lib.check(rc, allow=(0, 1, 2))
         out = (g, list(action), [s.as_dict() for s in stats], rc)
         return out + (x, y) if want_xy else out
+
+    # ---------------------------------------------------------- molecular dynamics
+    def _check_links(self, t: torch.Tensor):
+        if tuple(t.shape) != link_shape(self.dims, self.bc):
+            raise ValueError(f"expected links shape {link_shape(self.dims, self.bc)}, got {tuple(t.shape)}")
+
+    def kinetic_energy(self, mom: torch.Tensor, stream=None) -> float:
+        """1/2 sum P^a P^a over the links that enter D (FP64, on the GPU)."""
+        self._check_links(mom)
+        out = ctypes.c_double()
+        _lib.check(_lib.lib().mfq_kinetic_energy(self._h, _lib.dptr(mom), ctypes.byref(out), _lib.stream_ptr(stream)))
+        return out.value
+
+    def md_momenta(self, force: torch.Tensor, mom: torch.Tensor, eps: float, stream=None):
+        """mom -= eps * force on the links that enter D (in place)."""
+        self._check_links(force)
+        self._check_links(mom)
+        _lib.check(_lib.lib().mfq_md_momenta(self._h, _lib.dptr(force), _lib.dptr(mom), float(eps),
+                                            _lib.stream_ptr(stream)))
+
+    def md_links(self, mom: torch.Tensor, links: torch.Tensor, eps: float, stream=None):
+        """links <- exp(i eps P) links on the links that enter D (in place), and
+        the handle's packed links refreshed."""
+        self._check_links(mom)
+        self._check_links(links)
+        _lib.check(_lib.lib().mfq_md_links(self._h, _lib.dptr(mom), _lib.dptr(links), float(eps),
+                                          _lib.stream_ptr(stream)))
+
+    def hmc_trajectory(self, links: torch.Tensor, mom: torch.Tensor, phi: torch.Tensor, tau: float, n_steps: int,
+                       rand_uniform: float, params=None, stream=None, **kw):
+        """One leapfrog trajectory with Metropolis (links and mom updated in place,
+        restored on rejection); returns (result dict, status).  Solve keywords as
+        for solve()."""
+        self._check_links(links)
+        self._check_links(mom)
+        n = self._check_spinor(phi)
+        p = params if params is not None else make_params(**kw)
+        hp = _lib.HmcParams(float(tau), int(n_steps), float(rand_uniform))
+        res = _lib.HmcResult()
+        rc = _lib.lib().mfq_hmc_trajectory(self._h, _lib.dptr(links), _lib.dptr(mom), _lib.dptr(phi), n,
+                                           ctypes.byref(hp), ctypes.byref(p), ctypes.byref(res),
+                                           _lib.stream_ptr(stream))
+        _lib.check(rc, allow=(0, 1, 2))
+        return res.as_dict(), rc
 
     def set_autotune(self, on: bool):
         _lib.check(_lib.lib().mfq_set_autotune(self._h, int(bool(on))))

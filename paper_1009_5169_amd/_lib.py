@@ -17,8 +17,11 @@ LIB_PATH = os.path.join(_HERE, "libmfq.so")
 
 BC = {"sf": 0, "periodic": 1, "antiperiodic": 2}
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
-OPS = {"hop_eo": 0, "hop_oe": 1, "D": 2, "Ddag": 3, "DdagD": 4, "hop": 5, "hop_dag": 6}
-PRECOND = {"none": 0, "ptc": 1, "identity": 2, "blockcg": 3}
+OPS = {"hop_eo": 0, "hop_oe": 1, "D": 2, "Ddag": 3, "DdagD": 4, "hop": 5, "hop_dag": 6,
+       "schur": 7, "schur_dag": 8, "schur_normal": 9}
+ROUTE = {"full": 0, "schur": 1}
+PRECOND = {"none": 0, "ptc": 1, "identity": 2, "blockcg": 3, "bicgstab": 4, "gl_bicgstab": 5,
+           "bl_bicgstab": 6}
 
 MFQ_OK, MFQ_NOT_CONVERGED, MFQ_FELL_BACK = 0, 1, 2
 
@@ -36,13 +39,27 @@ class _Lattice(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("prec", ctypes.c_int),
                 ("reliable_delta", ctypes.c_double), ("precond", ctypes.c_int),
-                ("restart", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("restart", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("route", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_max_iter", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int),
                 ("true_rel_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int), ("inner_iters", ctypes.c_int), ("inner_calls", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class HmcParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("n_steps", ctypes.c_int), ("rand_uniform", ctypes.c_double)]
+
+
+class HmcResult(ctypes.Structure):
+    _fields_ = [("delta_h", ctypes.c_double), ("kinetic_old", ctypes.c_double), ("kinetic_new", ctypes.c_double),
+                ("action_old", ctypes.c_double), ("action_new", ctypes.c_double), ("accepted", ctypes.c_int),
+                ("force_evals", ctypes.c_int), ("solver_iters", ctypes.c_int), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -59,9 +76,19 @@ _SIGNATURES = {
     "mfq_dslash_prec": ([_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int, _P], ctypes.c_int),
     "mfq_solve_multi_rhs": ([_P, _P, _P, ctypes.c_int, ctypes.POINTER(SolveParams),
                              ctypes.POINTER(SolveStats), _P], ctypes.c_int),
+    "mfq_solve_dirac": ([_P, ctypes.c_int, _P, _P, ctypes.c_int, ctypes.POINTER(SolveParams),
+                         ctypes.POINTER(SolveStats), _P], ctypes.c_int),
     "mfq_fermion_force": ([_P, _P, ctypes.c_int, ctypes.POINTER(SolveParams), _P,
                            ctypes.POINTER(ctypes.c_double), _P, _P, ctypes.POINTER(SolveStats), _P],
                           ctypes.c_int),
+    "mfq_fermion_force_eo": ([_P, _P, ctypes.c_int, ctypes.POINTER(SolveParams), _P,
+                              ctypes.POINTER(ctypes.c_double), _P, _P, ctypes.POINTER(SolveStats), _P],
+                             ctypes.c_int),
+    "mfq_kinetic_energy": ([_P, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
+    "mfq_md_momenta": ([_P, _P, _P, ctypes.c_double, _P], ctypes.c_int),
+    "mfq_md_links": ([_P, _P, _P, ctypes.c_double, _P], ctypes.c_int),
+    "mfq_hmc_trajectory": ([_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(HmcParams), ctypes.POINTER(SolveParams),
+                            ctypes.POINTER(HmcResult), _P], ctypes.c_int),
     "mfq_time_hop": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
                       ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "mfq_set_autotune": ([_P, ctypes.c_int], ctypes.c_int),
@@ -150,6 +177,8 @@ def dptr(t: torch.Tensor) -> ctypes.c_void_p:
 
 
 def make_params(tol=1e-10, max_iter=20000, prec="fp32", reliable_delta=0.1, precond="none",
-                restart=16, check_every=0, use_graph=True) -> SolveParams:
+                restart=16, check_every=0, use_graph=True, route="full", inner_tol=0.0,
+                inner_max_iter=0) -> SolveParams:
     return SolveParams(float(tol), int(max_iter), PREC[prec], float(reliable_delta), PRECOND[precond],
-                       int(restart), int(check_every), int(bool(use_graph)))
+                       int(restart), int(check_every), int(bool(use_graph)), ROUTE[route], float(inner_tol),
+                       int(inner_max_iter))

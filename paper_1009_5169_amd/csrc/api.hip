@@ -163,6 +163,42 @@ int apply_op(mfq_handle* h, int op, Links<S> L, Field<S> in, Field<S> tmp, Field
       HIPCHK(run(EPI_D, in, tmp, 2, 0, mk));
       HIPCHK(run(EPI_D, tmp, out, 2, 1, mk));
       return MFQ_OK;
+    case MFQ_OP_SCHUR:
+    case MFQ_OP_SCHUR_DAG:
+    case MFQ_OP_SCHUR_NORMAL: {
+      // tmp_o = H_oe in_e; (tmp or out)_e = in_e - k^2 H_eo tmp_o; for the
+      // normal operator once more with H^+ from tmp_e
+      const double k2 = -h->lat.kappa * h->lat.kappa;
+      const int dag1 = op == MFQ_OP_SCHUR_DAG ? 1 : 0;
+      const bool normal = op == MFQ_OP_SCHUR_NORMAL;
+      a.par = 1;
+      a.in = in;
+      a.out = tmp;
+      a.dagger = dag1;
+      a.coef = 1.0;
+      HIPCHK(launch_hop<S, S>(EPI_HOP, a, sh1, st));
+      a.par = 0;
+      a.in = tmp;
+      a.self = in;
+      a.out = normal ? tmp : out;
+      a.coef = k2;
+      HIPCHK(launch_hop<S, S>(EPI_D, a, sh1, st));
+      if (normal) {
+        a.par = 1;
+        a.in = tmp;
+        a.out = tmp;
+        a.dagger = 1;
+        a.coef = 1.0;
+        HIPCHK(launch_hop<S, S>(EPI_HOP, a, sh1, st));
+        a.par = 0;
+        a.self = tmp;
+        a.out = out;
+        a.coef = k2;
+        HIPCHK(launch_hop<S, S>(EPI_D, a, sh1, st));
+      }
+      HIPCHK(launch_zero_parity<S>(h->g, out, n_rhs, 1, st));
+      return MFQ_OK;
+    }
     default:
       return fail(MFQ_ERR_ARG, "unknown operator");
   }
@@ -215,13 +251,18 @@ bool tune_cache_lookup(mfq_handle* h, int n, int prec, Shape* out) {
     int sb, nr, xcd, tc, ds;
     const char* bar = strchr(line, '|');
     if (!bar || std::string(line, bar - line) != key) continue;
-    if (sscanf(bar + 1, "%d %d %d %d %d", &sb, &nr, &xcd, &tc, &ds) == 5 && sb >= 64 && sb % 64 == 0 && nr >= 1 &&
-        sb * nr <= 512 && (tc == 0 || tc == 2 || tc == 4 || tc == 8 || tc == 16) &&
+    if (sscanf(bar + 1, "%d %d %d %d %d", &sb, &nr, &xcd, &tc, &ds) != 5) continue;
+    const bool rt = (xcd & 8) != 0;  // RHS in the thread: FP32 / FP16, plain tiles, 2..5 or 8 RHS
+    if (sb >= 64 && sb % 64 == 0 && nr >= 1 &&
+        (rt ? (prec != 8 && sb <= 256 && tc == 0 && ds == 0 && (xcd & 4) == 0 &&
+               (nr == 2 || nr == 3 || nr == 4 || nr == 5 || nr == 8))
+            : sb * nr <= 512) &&
+        (tc == 0 || tc == 2 || tc == 4 || tc == 8 || tc == 16) &&
         (ds == 0 || ((ds == 2 || ds == 4) && sb == 64 && ds * nr <= 8 && tc == 0 &&
                      nr * (ds - 1) * 24 * 64 * (prec == 8 ? 8 : 4) <= 65536))) {
       out->sb = sb;
       out->nr = nr;
-      out->xcd = xcd & 7;
+      out->xcd = xcd & 15;
       out->tc = tc;
       out->ds = ds;
       found = true;
@@ -277,6 +318,26 @@ int tuned_shape(mfq_handle* h, int n, int prec, Links<S> L, Field<S> src, Field<
         }
       }
     }
+  // RHS in the thread (FP32 / FP16): sb sites x nr RHS per thread
+  if (prec != 8)
+    for (int sb = 64; sb <= 256; sb *= 2)
+      for (int nr : {2, 3, 4, 5, 8}) {
+        if (nr > n) continue;
+        for (int xcd = 8; xcd < 12; ++xcd) {
+          Shape sh{sb, nr, xcd, 0, 0};
+          for (int i = 0; i < 2; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+          HIPCHK(hipEventRecord(h->ev0, st));
+          for (int i = 0; i < 10; ++i) HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+          HIPCHK(hipEventRecord(h->ev1, st));
+          HIPCHK(hipEventSynchronize(h->ev1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+          if (ms < best * 0.97f) {
+            best = ms;
+            best_sh = sh;
+          }
+        }
+      }
   *out = best_sh;
   h->tuned.push_back({n, prec, best_sh, best * 100.f});
   if (const char* path = getenv("MFQ_AUTOTUNE_CACHE")) {
@@ -304,18 +365,27 @@ struct Stat {
 // Batched CG on D^+D for n RHS, b in ws.b64, solution in ws.x64.
 // The inner recursion runs in storage S; the solution correction in SX.  Every
 // RHS has its own scalars; converged RHS are masked out of the vector work.
+//
+// schur: CG on D^+ D^ over the even sites instead (D^ = 1 - kappa^2 H_eo H_oe,
+// the Schur complement of the even/odd blocks of D); the vectors' odd halves
+// are never read by the vector kernels, so the odd half of t holds the
+// intermediate H_oe p of each half-dslash pair.
 template <typename S, typename SX>
 int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> in, double delta, hipStream_t st,
-           mfq_solve_stats* stats) {
+           mfq_solve_stats* stats, bool schur = false) {
   Workspace& w = h->ws;
-  const Geom& g = h->g;
+  Geom g = h->g;
+  if (schur) g.npar = 1;
   Shape sh;
   int rc0 = tuned_shape<S, SX>(h, n, (int)sizeof(S), in.L, in.p, in.t, st, &sh);
   if (rc0 != MFQ_OK) return rc0;
+  // the vector kernels take (sites x RHS) workgroups: with the RHS-in-thread
+  // hopping shape they use the default one
+  const Shape shv = (sh.xcd & 8) ? default_shape(n) : sh;
   const double mk = -h->lat.kappa;
   const double tol2 = P->tol * P->tol;
   const double delta2 = delta * delta;
-  const int nb_full = (2 * g.vh + sh.sb - 1) / sh.sb;
+  const int nb_full = (g.npar * g.vh + shv.sb - 1) / shv.sb;
   // the FP64 true-residual launches: the tuned FP64 shape if one is known,
   // else the inner shape with the direction split dropped where its LDS
   // partial sums would not fit at FP64 width
@@ -323,19 +393,21 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   if (sizeof(S) != 8 && !(h->autotune && tune_cache_lookup(h, n, 8, &sh64))) {
     sh64 = sh;
     if (sh64.ds && (size_t)sh64.nr * (sh64.ds - 1) * 24 * 64 * sizeof(double) > 65536) sh64.ds = 0;
+    if (sh64.xcd & 8) sh64 = default_shape(n);  // RHS in the thread is an FP32 / FP16 form
   }
-  const int nb64 = hop_grid_x(g, sh64, 2);
+  const int nb64 = hop_grid_x(g, sh64, schur ? 0 : 2);
+  const double k2 = -h->lat.kappa * h->lat.kappa;
   CgScalars* sc = (CgScalars*)w.sc.ptr;
   Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), r64 = w.r64.view(g), t64 = w.t64.view(g);
 
   // initial state: x = 0, r = b, p = r
-  HIPCHK(launch_init_residual(g, b64, r64, part_slot(h, 0), n, sh, st));
+  HIPCHK(launch_init_residual(g, b64, r64, part_slot(h, 0), n, shv, st));
   Partials p0{part_slot(h, 0), nb_full};
   HIPCHK(launch_finish(FIN_INIT, &p0, 1, n, sc, nullptr, tol2, delta2, st));
   HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, field_chunks<double>(g, n) * sizeof(d2), st));
   HIPCHK(hipMemsetAsync(in.x.data, 0, field_chunks<SX>(g, n) * sizeof(typename Store<SX>::chunk), st));
   if (sizeof(SX) == 2) HIPCHK(hipMemsetAsync(in.x.norm, 0, (size_t)n * 2 * g.vs * sizeof(float), st));
-  HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, sh, st));
+  HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, shv, st));
 
   HopArgs<S, SX> a = hop_args<S, SX>(h, in.L, n);
   a.sc = sc;
@@ -348,9 +420,56 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   // Both parities per launch: the D half reads only p, the D^+ half only t.
   // On small lattices alpha is reduced inside the update kernel (one launch
   // fewer); larger ones use the finishing kernel.
-  const int nb2 = hop_grid_x(g, sh, 2);
+  const int nb2 = hop_grid_x(g, sh, schur ? 0 : 2);
   const bool fuse_alpha = nb2 <= 256;
+  // Schur form: 4 single-parity launches per iteration (t_o = H_oe p_e;
+  // t_e = p_e - k^2 H_eo t_o with |t_e|^2; t_o = H^+_oe t_e; Ap = t_e -
+  // k^2 H^+_eo t_o with the r, x update and |r|^2)
+  auto iteration_schur = [&](hipStream_t st) -> int {
+    a.skip_state = ST_WAIT;
+    a.apart = nullptr;
+    a.part = nullptr;
+    a.in = in.p;
+    a.out = in.t;
+    a.dagger = 0;
+    a.par = 1;
+    a.coef = 1.0;
+    HIPCHK(launch_hop<S, SX>(EPI_HOP, a, sh, st));
+    a.in = in.t;
+    a.self = in.p;
+    a.par = 0;
+    a.coef = k2;
+    a.part = part_slot(h, 0);
+    HIPCHK(launch_hop<S, SX>(EPI_D, a, sh, st));
+    if (!fuse_alpha) {
+      Partials pa{part_slot(h, 0), nb2};
+      HIPCHK(launch_finish(FIN_ALPHA, &pa, 1, n, sc, nullptr, tol2, delta2, st));
+    }
+    a.in = in.t;
+    a.out = in.t;
+    a.dagger = 1;
+    a.par = 1;
+    a.coef = 1.0;
+    a.part = nullptr;
+    HIPCHK(launch_hop<S, SX>(EPI_HOP, a, sh, st));
+    a.self = in.t;
+    a.out = in.r;
+    a.x = in.x;
+    a.p = in.p;
+    a.par = 0;
+    a.coef = k2;
+    a.part = part_slot(h, 2);
+    a.apart = fuse_alpha ? part_slot(h, 0) : nullptr;
+    a.anblk = nb2;
+    HIPCHK(launch_hop<S, SX>(EPI_CGUPD, a, sh, st));
+    Partials pb{part_slot(h, 2), nb2};
+    HIPCHK(launch_finish(FIN_BETA, &pb, 1, n, sc, nullptr, tol2, delta2, st));
+    HIPCHK(launch_xpay_p<S>(g, in.r, in.p, sc, n, shv, st));
+    return MFQ_OK;
+  };
   auto iteration = [&](hipStream_t st) -> int {
+    if (schur) return iteration_schur(st);
+    a.coef = mk;
     // t = D p, partial |t|^2 = p^+ D^+ D p
     a.in = a.self = in.p;
     a.out = in.t;
@@ -376,7 +495,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     HIPCHK(launch_hop<S, SX>(EPI_CGUPD, a, sh, st));
     Partials pb{part_slot(h, 2), nb2};
     HIPCHK(launch_finish(FIN_BETA, &pb, 1, n, sc, nullptr, tol2, delta2, st));
-    HIPCHK(launch_xpay_p<S>(g, in.r, in.p, sc, n, sh, st));
+    HIPCHK(launch_xpay_p<S>(g, in.r, in.p, sc, n, shv, st));
     return MFQ_OK;
   };
 
@@ -384,8 +503,42 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
   // recompute r64 = b - A x64 in FP64, and continue the inner recursion from
   // it (RHS that meet tol become DONE).
   auto reliable_update = [&](int mode) -> int {
-    HIPCHK(launch_fold<SX>(g, in.x, x64, sc, n, mode, sh, st));
+    HIPCHK(launch_fold<SX>(g, in.x, x64, sc, n, mode, shv, st));
     a64.upd_mode = mode;
+    if (schur) {
+      // t_o = H_oe x_e; t_e = x_e - k^2 H_eo t_o; t_o = H^+_oe t_e;
+      // r_e = b_e - (t_e - k^2 H^+_eo t_o)
+      a64.part = nullptr;
+      a64.in = x64;
+      a64.out = t64;
+      a64.dagger = 0;
+      a64.par = 1;
+      a64.coef = 1.0;
+      HIPCHK(launch_hop<double, double>(EPI_HOP, a64, sh64, st));
+      a64.in = t64;
+      a64.self = x64;
+      a64.par = 0;
+      a64.coef = k2;
+      HIPCHK(launch_hop<double, double>(EPI_D, a64, sh64, st));
+      a64.in = t64;
+      a64.dagger = 1;
+      a64.par = 1;
+      a64.coef = 1.0;
+      HIPCHK(launch_hop<double, double>(EPI_HOP, a64, sh64, st));
+      a64.self = t64;
+      a64.bvec = b64;
+      a64.r64 = r64;
+      a64.par = 0;
+      a64.coef = k2;
+      a64.part = part_slot(h, 0);
+      HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh64, st));
+      Partials pt{part_slot(h, 0), nb64};
+      HIPCHK(launch_finish(mode == UPD_ALL ? FIN_TRUE : FIN_TRUE_FLAGGED, &pt, 1, n, sc, nullptr, tol2, delta2,
+                           st));
+      HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, shv, st));
+      return MFQ_OK;
+    }
+    a64.coef = mk;
     a64.in = a64.self = x64;
     a64.out = t64;
     a64.dagger = 0;
@@ -400,7 +553,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
     HIPCHK(launch_hop<double, double>(EPI_RES, a64, sh64, st));
     Partials pt{part_slot(h, 0), nb64};
     HIPCHK(launch_finish(mode == UPD_ALL ? FIN_TRUE : FIN_TRUE_FLAGGED, &pt, 1, n, sc, nullptr, tol2, delta2, st));
-    HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, sh, st));
+    HIPCHK(launch_restart<S>(g, r64, in.r, in.p, sc, n, shv, st));
     return MFQ_OK;
   };
 
@@ -413,7 +566,7 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
       return MFQ_OK;
     }
     std::vector<uintptr_t> key = {(uintptr_t)sizeof(S), (uintptr_t)sizeof(SX), (uintptr_t)n, (uintptr_t)k,
-                                  (uintptr_t)fuse_alpha,
+                                  (uintptr_t)fuse_alpha, (uintptr_t)schur,
                                   (uintptr_t)in.r.data, (uintptr_t)in.p.data, (uintptr_t)in.t.data,
                                   (uintptr_t)in.x.data, (uintptr_t)in.L.data, (uintptr_t)w.part.ptr,
                                   (uintptr_t)sc, bits(tol2), bits(delta2), (uintptr_t)sh.sb,
@@ -520,17 +673,25 @@ int run_cg(mfq_handle* h, int n, const mfq_solve_params* P, InnerFields<S, SX> i
 
 int check_params(const mfq_solve_params* P) {
   if (!P) return fail(MFQ_ERR_ARG, "params is NULL");
+  if (P->route != MFQ_ROUTE_FULL && P->route != MFQ_ROUTE_SCHUR) return fail(MFQ_ERR_ARG, "unknown route");
+  if (P->route == MFQ_ROUTE_SCHUR && P->precond != MFQ_PC_NONE && !is_bicgstab(P->precond))
+    return fail(MFQ_ERR_ARG, "the Schur route runs batched CG or the BiCGStab solvers only");
   if (!(P->tol > 0.0) || P->tol >= 1.0) return fail(MFQ_ERR_ARG, "tol must be in (0, 1)");
   if (P->max_iter < 1) return fail(MFQ_ERR_ARG, "max_iter must be >= 1");
   if (P->prec < MFQ_PREC_FP64 || P->prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
-  if (P->precond < MFQ_PC_NONE || P->precond > MFQ_PC_BLOCKCG) return fail(MFQ_ERR_ARG, "unknown solver selection");
+  if (P->precond < MFQ_PC_NONE || P->precond > MFQ_PC_BL_BICGSTAB) return fail(MFQ_ERR_ARG, "unknown solver selection");
   if (P->restart > 32) return fail(MFQ_ERR_ARG, "restart must be <= 32");
   return MFQ_OK;
 }
 
-// Solve D^+D x64 = b64 for n RHS at the requested precision.
-int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
+// Solve D^+D x64 = b64 for n RHS at the requested precision (schur: D^+D^
+// on the even sites).
+int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats,
+                 bool schur) {
   if (int rc = need_su3(h, P->prec, P->precond)) return rc;
+  if (schur && P->precond != MFQ_PC_NONE) return fail(MFQ_ERR_ARG, "Schur solves run batched CG only");
+  if (is_bicgstab(P->precond))
+    return fail(MFQ_ERR_ARG, "the BiCGStab solvers solve D itself, not the normal equations");
   if (P->precond == MFQ_PC_PTC || P->precond == MFQ_PC_IDENTITY) return run_fgmres(h, n, P, st, stats);
   if (P->precond == MFQ_PC_BLOCKCG) return run_block_cg(h, n, P, st, stats);
   Workspace& w = h->ws;
@@ -544,7 +705,7 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       HIPCHK(w.td.alloc(g, n));
       InnerFields<double, double> in{links_d(h), w.rd.view(g), w.pd.view(g), w.td.view(g), w.xd.view(g)};
       // FP64: no reliable updates; the true residual is checked at the end
-      return run_cg<double, double>(h, n, P, in, 0.0, st, stats);
+      return run_cg<double, double>(h, n, P, in, 0.0, st, stats, schur);
     }
     case MFQ_PREC_FP32_RELIABLE: {
       HIPCHK(w.xs.alloc(g, n));
@@ -552,7 +713,7 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       HIPCHK(w.ps.alloc(g, n));
       HIPCHK(w.ts.alloc(g, n));
       InnerFields<float, float> in{links_f(h), w.rs.view(g), w.ps.view(g), w.ts.view(g), w.xs.view(g)};
-      return run_cg<float, float>(h, n, P, in, delta, st, stats);
+      return run_cg<float, float>(h, n, P, in, delta, st, stats, schur);
     }
     default: {
       HIPCHK(w.xs.alloc(g, n));
@@ -560,9 +721,132 @@ int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       HIPCHK(w.ph.alloc(g, n));
       HIPCHK(w.th.alloc(g, n));
       InnerFields<_Float16, float> in{links_h(h), w.rh.view(g), w.ph.view(g), w.th.view(g), w.xs.view(g)};
-      return run_cg<_Float16, float>(h, n, P, in, delta, st, stats);
+      return run_cg<_Float16, float>(h, n, P, in, delta, st, stats, schur);
     }
   }
+}
+
+// Solve D z = b (dagger 0) or D^+ z = b (dagger 1) for the full field b in
+// ws.b64 through the even/odd Schur complement (route S): with
+// b'_e = b_e + kappa H_eo b_o (H^+ for dagger), CG on D^+D^ gives z_e =
+// D^-1 b'_e, and z_o = b_o + kappa H_oe z_e.  For dagger, D^^+ = g5 D^ g5, so
+// w = g5 z_e solves D^ w = g5 b'_e and the same CG serves.  z lands in
+// ws.x64; b64, r64, t64 and y64 are overwritten.
+int schur_solve(mfq_handle* h, int n, int dagger, const mfq_solve_params* P, hipStream_t st,
+                mfq_solve_stats* stats) {
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  Geom ge = g;
+  ge.npar = 1;
+  const double k = h->lat.kappa;
+  Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), t64 = w.t64.view(g), y64 = w.y64.view(g);
+  const Shape sh1 = default_shape(n);
+  HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n);
+  HIPCHK(launch_convert<double, double>(g, b64, y64, 0, n, sh1, st));  // keeps b_o for the end
+  a.in = a.self = y64;
+  a.out = t64;
+  a.par = 0;
+  a.dagger = dagger;
+  a.coef = k;
+  HIPCHK(launch_hop<double, double>(EPI_D, a, sh1, st));  // t_e = b'_e
+  if (dagger) HIPCHK(launch_convert<double, double>(ge, t64, t64, 1, n, sh1, st));
+  int rc;
+  if (is_bicgstab(P->precond)) {
+    // the paper's solvers work on D^ itself
+    HIPCHK(launch_convert<double, double>(ge, t64, b64, 0, n, sh1, st));
+    rc = run_bicgstab_schur(h, n, bicgstab_kind(P->precond), P, st, stats);
+    if (rc < 0) return rc;
+    goto reconstruct;
+  }
+  // normal-equation right-hand side D^^+ t_e
+  a.in = a.out = t64;
+  a.par = 1;
+  a.dagger = 1;
+  a.coef = 1.0;
+  HIPCHK(launch_hop<double, double>(EPI_HOP, a, sh1, st));
+  a.self = t64;
+  a.out = b64;
+  a.par = 0;
+  a.coef = -k * k;
+  HIPCHK(launch_hop<double, double>(EPI_D, a, sh1, st));
+  rc = solve_packed(h, n, P, st, stats, true);
+  if (rc < 0) return rc;
+reconstruct:
+  if (dagger) HIPCHK(launch_convert<double, double>(ge, x64, x64, 1, n, sh1, st));
+  a.in = x64;
+  a.self = y64;
+  a.out = x64;
+  a.par = 1;
+  a.dagger = dagger;
+  a.coef = k;
+  HIPCHK(launch_hop<double, double>(EPI_D, a, sh1, st));  // z_o
+  return rc;
+}
+
+// Merge the statistics of two solves run one after the other.
+void merge_stats(mfq_solve_stats* a, const mfq_solve_stats* b, int n) {
+  for (int r = 0; r < n; ++r) {
+    a[r].iters += b[r].iters;
+    a[r].reliable_updates += b[r].reliable_updates;
+    a[r].inner_iters += b[r].inner_iters;
+    a[r].inner_calls += b[r].inner_calls;
+    if (b[r].status != MFQ_OK) a[r].status = b[r].status;
+  }
+}
+
+// ||b - D^+D x64|| / ||b|| per RHS in FP64 for b in b64 (t64, r64 scratch).
+int full_residual(mfq_handle* h, int n, hipStream_t st, mfq_solve_stats* stats) {
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  Shape sh;
+  if (int rc = fp64_hop_shape(h, n, st, &sh)) return rc;
+  const Shape sh1 = default_shape(n);
+  const int nb_full = (g.npar * g.vh + sh1.sb - 1) / sh1.sb;
+  std::vector<double> bn(n), rn(n);
+  HIPCHK(launch_norm2(g, w.b64.view(g), part_slot(h, 0), n, sh1, nb_full, st));
+  Partials p0{part_slot(h, 0), nb_full};
+  HIPCHK(launch_finish(FIN_STORE, &p0, 1, n, nullptr, (double*)w.sums.ptr, 0.0, 0.0, st));
+  HIPCHK(hipMemcpyAsync(bn.data(), w.sums.ptr, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n);
+  a.in = a.self = w.x64.view(g);
+  a.out = w.t64.view(g);
+  a.par = 2;
+  a.coef = -h->lat.kappa;
+  HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+  a.in = a.self = w.t64.view(g);
+  a.bvec = w.b64.view(g);
+  a.r64 = w.r64.view(g);
+  a.dagger = 1;
+  a.part = part_slot(h, 1);
+  HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
+  Partials p1{part_slot(h, 1), hop_grid_x(g, sh, 2)};
+  HIPCHK(launch_finish(FIN_STORE, &p1, 1, n, nullptr, (double*)w.sums.ptr, 0.0, 0.0, st));
+  HIPCHK(hipMemcpyAsync(rn.data(), w.sums.ptr, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int r = 0; r < n; ++r) stats[r].true_rel_resid = bn[r] > 0 ? sqrt(rn[r] / bn[r]) : 0.0;
+  return MFQ_OK;
+}
+
+// The end of a force evaluation: force_dev = sum_i f[x_i, y_i] (Eq. 3),
+// action_host[i] = |x_i|^2 over the parities gn covers, X and Y unpacked if
+// asked for.  Host-blocking.
+int force_tail(mfq_handle* h, Field<double> X, Field<double> Y, const Geom& gn, int n, double* force_dev,
+               double* action_host, double* x_dev, double* y_dev, hipStream_t st) {
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  const Shape sh = default_shape(n);
+  const size_t force_bytes = (size_t)4 * h->n_slices * g.lx * g.ly * g.lz * 9 * sizeof(d2);
+  HIPCHK(hipMemsetAsync(force_dev, 0, force_bytes, st));
+  HIPCHK(launch_force(g, links_d(h), X, Y, n, h->lat.kappa, force_dev, h->n_slices, st));
+  const int nb_full = (gn.npar * gn.vh + sh.sb - 1) / sh.sb;
+  HIPCHK(launch_norm2(gn, X, part_slot(h, 0), n, sh, nb_full, st));
+  Partials p0{part_slot(h, 0), nb_full};
+  HIPCHK(launch_finish(FIN_STORE, &p0, 1, n, nullptr, (double*)w.sums.ptr, 0.0, 0.0, st));
+  if (x_dev) HIPCHK(launch_unpack_spinor(g, X, x_dev, n, st));
+  if (y_dev) HIPCHK(launch_unpack_spinor(g, Y, y_dev, n, st));
+  if (action_host) HIPCHK(hipMemcpyAsync(action_host, w.sums.ptr, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return MFQ_OK;
 }
 
 int fp64_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out) {
@@ -623,6 +907,7 @@ int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mf
   g.td = lat->bc == MFQ_BC_SF ? lat->dims[3] - 1 : lat->dims[3];
   g.t0 = lat->bc == MFQ_BC_SF ? 1 : 0;
   g.lxh = g.lx / 2;
+  g.npar = 2;
   g.vh = g.lxh * g.ly * g.lz * g.td;
   {
     int gr = (g.vh + 15) / 16;  // 256-byte granules of a 16-byte-per-site array
@@ -661,7 +946,7 @@ int mfq_dslash_prec(mfq_handle* h, int op, int prec, const double* in_dev, doubl
                     void* stream) {
   if (!h || !in_dev || !out_dev) return fail(MFQ_ERR_ARG, "NULL argument");
   if (n_rhs < 1) return fail(MFQ_ERR_ARG, "n_rhs must be >= 1");
-  if (op < MFQ_OP_HOP_EO || op > MFQ_OP_HOP_DAG) return fail(MFQ_ERR_ARG, "unknown operator");
+  if (op < MFQ_OP_HOP_EO || op > MFQ_OP_SCHUR_NORMAL) return fail(MFQ_ERR_ARG, "unknown operator");
   if (prec < MFQ_PREC_FP64 || prec > MFQ_PREC_FP16_REFINE) return fail(MFQ_ERR_ARG, "unknown precision");
   hipStream_t st = (hipStream_t)stream;
   int rc = need_su3(h, prec, MFQ_PC_NONE);
@@ -712,13 +997,58 @@ int mfq_solve_multi_rhs(mfq_handle* h, const double* b_dev, double* x_dev, int n
   hipStream_t st = (hipStream_t)stream;
   if ((rc = ensure_fp64_fields(h, n_rhs))) return rc;
   if ((rc = pack_checked(h, b_dev, n_rhs, 0, st))) return rc;
-  rc = solve_packed(h, n_rhs, params, st, stats_host);
-  if (rc < 0) return rc;
+  if (params->route == MFQ_ROUTE_SCHUR || is_bicgstab(params->precond)) {
+    // x = D^-1 (D^+)^-1 b: two even/odd solves, then the full residual
+    std::vector<mfq_solve_stats> s1(n_rhs), s2(n_rhs);
+    const int rc1 = schur_solve(h, n_rhs, 1, params, st, s1.data());
+    if (rc1 < 0) return rc1;
+    const Geom& g = h->g;
+    HIPCHK(launch_convert<double, double>(g, h->ws.x64.view(g), h->ws.b64.view(g), 0, n_rhs,
+                                          default_shape(n_rhs), st));
+    const int rc2 = schur_solve(h, n_rhs, 0, params, st, s2.data());
+    if (rc2 < 0) return rc2;
+    merge_stats(s1.data(), s2.data(), n_rhs);
+    HIPCHK(launch_pack_spinor<double>(g, b_dev, h->ws.b64.view(g), n_rhs, 0, nullptr, st));
+    if ((rc = full_residual(h, n_rhs, st, s1.data()))) return rc;
+    rc = rc1 != MFQ_OK ? rc1 : rc2;
+    if (stats_host)
+      for (int r = 0; r < n_rhs; ++r) stats_host[r] = s1[r];
+  } else {
+    rc = solve_packed(h, n_rhs, params, st, stats_host);
+    if (rc < 0) return rc;
+  }
   HIPCHK(launch_unpack_spinor(h->g, h->ws.x64.view(h->g), x_dev, n_rhs, st));
   HIPCHK(hipStreamSynchronize(st));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats_host)
     for (int r = 0; r < n_rhs; ++r) stats_host[r].seconds = secs;
+  return rc;
+}
+
+int mfq_solve_dirac(mfq_handle* h, int dagger, const double* b_dev, double* x_dev, int n_rhs,
+                    const mfq_solve_params* params, mfq_solve_stats* stats_host, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!h || !b_dev || !x_dev) return fail(MFQ_ERR_ARG, "NULL argument");
+  if (n_rhs < 1) return fail(MFQ_ERR_ARG, "n_rhs must be >= 1");
+  if (dagger != 0 && dagger != 1) return fail(MFQ_ERR_ARG, "dagger must be 0 or 1");
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (params->precond != MFQ_PC_NONE && !is_bicgstab(params->precond))
+    return fail(MFQ_ERR_ARG, "mfq_solve_dirac runs CG through the Schur complement or the BiCGStab solvers");
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = ensure_fp64_fields(h, n_rhs))) return rc;
+  if ((rc = pack_checked(h, b_dev, n_rhs, 0, st))) return rc;
+  std::vector<mfq_solve_stats> s1(n_rhs);
+  rc = schur_solve(h, n_rhs, dagger, params, st, s1.data());
+  if (rc < 0) return rc;
+  HIPCHK(launch_unpack_spinor(h->g, h->ws.x64.view(h->g), x_dev, n_rhs, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats_host)
+    for (int r = 0; r < n_rhs; ++r) {
+      stats_host[r] = s1[r];
+      stats_host[r].seconds = secs;
+    }
   return rc;
 }
 
@@ -732,34 +1062,99 @@ int mfq_fermion_force(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if ((rc = ensure_fp64_fields(h, n_rhs))) return rc;
-  // b = g5 phi;  Z = (D^+D)^-1 b;  Y = g5 Z;  X = D^+ Y
-  if ((rc = pack_checked(h, phi_dev, n_rhs, 1, st))) return rc;
-  rc = solve_packed(h, n_rhs, params, st, stats_host);
-  if (rc < 0) return rc;
   Workspace& w = h->ws;
   const Geom& g = h->g;
   const Shape sh = default_shape(n_rhs);
+  Field<double> Y, X;
+  if (params->route == MFQ_ROUTE_SCHUR || is_bicgstab(params->precond)) {
+    // Alg. 2 literally: D X = Phi, then D^+ Y = X, each through the Schur complement
+    HIPCHK(w.aux64.alloc(g, n_rhs));
+    if ((rc = pack_checked(h, phi_dev, n_rhs, 0, st))) return rc;
+    std::vector<mfq_solve_stats> s2(n_rhs);
+    std::vector<mfq_solve_stats> s1(n_rhs);
+    const int rc1 = schur_solve(h, n_rhs, 0, params, st, s1.data());
+    if (rc1 < 0) return rc1;
+    X = w.aux64.view(g);
+    HIPCHK(launch_convert<double, double>(g, w.x64.view(g), X, 0, n_rhs, sh, st));
+    HIPCHK(launch_convert<double, double>(g, w.x64.view(g), w.b64.view(g), 0, n_rhs, sh, st));
+    const int rc2 = schur_solve(h, n_rhs, 1, params, st, s2.data());
+    if (rc2 < 0) return rc2;
+    merge_stats(s1.data(), s2.data(), n_rhs);
+    for (int r = 0; r < n_rhs; ++r) s1[r].true_rel_resid = s2[r].true_rel_resid;
+    if (stats_host)
+      for (int r = 0; r < n_rhs; ++r) stats_host[r] = s1[r];
+    rc = rc1 != MFQ_OK ? rc1 : rc2;
+    Y = w.x64.view(g);
+  } else {
+    // b = g5 phi;  Z = (D^+D)^-1 b;  Y = g5 Z;  X = D^+ Y
+    if ((rc = pack_checked(h, phi_dev, n_rhs, 1, st))) return rc;
+    rc = solve_packed(h, n_rhs, params, st, stats_host);
+    if (rc < 0) return rc;
+    Y = w.y64.view(g);
+    X = w.t64.view(g);
+    HIPCHK(launch_convert<double, double>(g, w.x64.view(g), Y, 1, n_rhs, sh, st));
+    HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n_rhs);
+    a.in = a.self = Y;
+    a.out = X;
+    a.dagger = 1;
+    a.coef = -h->lat.kappa;
+    a.par = 2;
+    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+  }
+  const int rt = force_tail(h, X, Y, g, n_rhs, force_dev, action_host, x_dev, y_dev, st);
+  if (rt) return rt;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats_host)
+    for (int r = 0; r < n_rhs; ++r) stats_host[r].seconds = secs;
+  return rc;
+}
+
+int mfq_fermion_force_eo(mfq_handle* h, const double* phi_dev, int n_rhs, const mfq_solve_params* params,
+                         double* force_dev, double* action_host, double* x_dev, double* y_dev,
+                         mfq_solve_stats* stats_host, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!h || !phi_dev || !force_dev) return fail(MFQ_ERR_ARG, "NULL argument");
+  if (n_rhs < 1) return fail(MFQ_ERR_ARG, "n_rhs must be >= 1");
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (params->precond != MFQ_PC_NONE) return fail(MFQ_ERR_ARG, "the even/odd action runs batched CG only");
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = ensure_fp64_fields(h, n_rhs))) return rc;
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  Geom ge = g;
+  ge.npar = 1;
+  const Shape sh = default_shape(n_rhs);
+  const double k = h->lat.kappa;
+  // b_e = g5 phi_e;  Z = (D^^+ D^)^-1 b_e;  Y_e = g5 Z;  X_e = D^^+ Y_e
+  if ((rc = pack_checked(h, phi_dev, n_rhs, 1, st))) return rc;
+  rc = solve_packed(h, n_rhs, params, st, stats_host, true);
+  if (rc < 0) return rc;
   Field<double> Y = w.y64.view(g), X = w.t64.view(g);
-  HIPCHK(launch_convert<double, double>(g, w.x64.view(g), Y, 1, n_rhs, sh, st));
+  HIPCHK(launch_convert<double, double>(ge, w.x64.view(g), Y, 1, n_rhs, sh, st));
   HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n_rhs);
-  a.in = a.self = Y;
+  a.in = Y;
   a.out = X;
+  a.par = 1;
   a.dagger = 1;
-  a.coef = -h->lat.kappa;
-  a.par = 2;
-  HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-  const size_t force_bytes = (size_t)4 * h->n_slices * g.lx * g.ly * g.lz * 9 * sizeof(d2);
-  HIPCHK(hipMemsetAsync(force_dev, 0, force_bytes, st));
-  HIPCHK(launch_force(g, links_d(h), X, Y, n_rhs, h->lat.kappa, force_dev, h->n_slices, st));
-  const int nb_full = (2 * g.vh + sh.sb - 1) / sh.sb;
-  HIPCHK(launch_norm2(g, X, part_slot(h, 0), n_rhs, sh, nb_full, st));
-  Partials p0{part_slot(h, 0), nb_full};
-  HIPCHK(launch_finish(FIN_STORE, &p0, 1, n_rhs, nullptr, (double*)w.sums.ptr, 0.0, 0.0, st));
-  if (x_dev) HIPCHK(launch_unpack_spinor(g, X, x_dev, n_rhs, st));
-  if (y_dev) HIPCHK(launch_unpack_spinor(g, Y, y_dev, n_rhs, st));
-  if (action_host)
-    HIPCHK(hipMemcpyAsync(action_host, w.sums.ptr, sizeof(double) * n_rhs, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  a.coef = 1.0;
+  HIPCHK(launch_hop<double, double>(EPI_HOP, a, sh, st));  // X_o = H^+_oe Y_e (scratch)
+  a.in = X;
+  a.self = Y;
+  a.par = 0;
+  a.coef = -k * k;
+  HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));  // X_e = Y_e - k^2 H^+_eo X_o
+  // the odd sites: X_o = k H_oe X_e, Y_o = k H^+_oe Y_e
+  a.in = a.out = X;
+  a.par = 1;
+  a.dagger = 0;
+  a.coef = k;
+  HIPCHK(launch_hop<double, double>(EPI_HOP, a, sh, st));
+  a.in = a.out = Y;
+  a.dagger = 1;
+  HIPCHK(launch_hop<double, double>(EPI_HOP, a, sh, st));
+  const int rt = force_tail(h, X, Y, ge, n_rhs, force_dev, action_host, x_dev, y_dev, st);
+  if (rt) return rt;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats_host)
     for (int r = 0; r < n_rhs; ++r) stats_host[r].seconds = secs;
@@ -855,13 +1250,14 @@ int mfq_set_autotune(mfq_handle* h, int on) {
 void mfq_destroy(mfq_handle* h) {
   if (!h) return;
   Workspace& w = h->ws;
-  for (auto* f : {&w.b64, &w.x64, &w.r64, &w.t64, &w.y64, &w.xd, &w.rd, &w.pd, &w.td}) f->free_all();
+  for (auto* f : {&w.b64, &w.x64, &w.r64, &w.t64, &w.y64, &w.aux64, &w.xd, &w.rd, &w.pd, &w.td}) f->free_all();
   for (auto* f : {&w.xs, &w.rs, &w.ps, &w.ts}) f->free_all();
   for (auto* f : {&w.rh, &w.ph, &w.th}) f->free_all();
   release(w.part);
   release(w.sc);
   release(w.sums);
   release(w.bad);
+  for (auto* b : {&w.md_part, &w.md_u0, &w.md_p0, &w.md_force}) release(*b);
   if (w.host_sc) (void)hipHostFree(w.host_sc);
   release(h->links64);
   release(h->links32);

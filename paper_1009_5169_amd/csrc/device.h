@@ -80,6 +80,9 @@ struct Geom {
   // 32^3 x 64) all components of a site fall in one L2 channel and set and
   // evict each other.
   int vs;
+  // Parities the vector kernels cover: 2 (every site), or 1 (the even sites
+  // only: the even/odd Schur-complement solves).
+  int npar;
 };
 
 struct Coords {

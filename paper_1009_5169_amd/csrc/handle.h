@@ -14,10 +14,12 @@ namespace mfq {
 
 struct Workspace {
   OwnedField<double> b64, x64, r64, t64, y64;
+  OwnedField<double> aux64;  // route S force: X while Y is solved for
   OwnedField<double> xd, rd, pd, td;
   OwnedField<float> xs, rs, ps, ts;
   OwnedField<_Float16> rh, ph, th;
   DevBuf part, sc, sums, bad;
+  DevBuf md_part, md_u0, md_p0, md_force;  // molecular dynamics (md.hip)
   int cap_part = 0;  // RHS capacity of the partial-sum slots
   int nblk_max = 0;
   CgScalars* host_sc = nullptr;
@@ -84,7 +86,23 @@ int ensure_fp64_fields(mfq_handle* h, int n);
 int check_params(const mfq_solve_params* P);
 int need_su3(mfq_handle* h, int prec, int precond);
 int pack_checked(mfq_handle* h, const double* canon, int n_rhs, int gamma5, hipStream_t st);
-int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
+int solve_packed(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats,
+                 bool schur = false);
+// D z = b (dagger 0) or D^+ z = b (dagger 1) through the even/odd Schur
+// complement: b in ws.b64, z in ws.x64 (b64, r64, t64, y64 overwritten)
+int schur_solve(mfq_handle* h, int n, int dagger, const mfq_solve_params* P, hipStream_t st,
+                mfq_solve_stats* stats);
+void merge_stats(mfq_solve_stats* a, const mfq_solve_stats* b, int n);
+// the paper's BiCGStab solvers on the even/odd system (bicgstab.hip): D^ x_e =
+// b_e for b in ws.b64, x into ws.x64 (even sites); kind 0 plain, 1 global, 2 block
+int run_bicgstab_schur(mfq_handle* h, int n, int kind, const mfq_solve_params* P, hipStream_t st,
+                       mfq_solve_stats* stats);
+inline bool is_bicgstab(int precond) {
+  return precond == MFQ_PC_BICGSTAB || precond == MFQ_PC_GL_BICGSTAB || precond == MFQ_PC_BL_BICGSTAB;
+}
+inline int bicgstab_kind(int precond) { return precond - MFQ_PC_BICGSTAB; }
+// per-RHS FP64 |b - D^+D x| / |b| into stats[].true_rel_resid (b in b64, x in x64)
+int full_residual(mfq_handle* h, int n, hipStream_t st, mfq_solve_stats* stats);
 // flexible GMRES with the learned (or identity) preconditioner (fgmres.hip)
 int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
 int run_block_cg(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);

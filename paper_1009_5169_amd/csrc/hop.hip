@@ -250,6 +250,176 @@ __global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
   }
 }
 
+// RHS in the thread (order flag bit 3, FP32 / FP16 storage): each thread
+// computes one site for R right-hand sides.  Every link is loaded and its
+// third row rebuilt once per thread and applied to the R neighbour spinors,
+// and the index arithmetic of each direction is shared by them, so a link
+// load serves all R pseudo-fermions from registers rather than through the
+// L1.  Groups of R RHS are grid.y; a ragged last group computes clamped
+// copies of its last RHS and stores nothing for them.
+template <int MU, int R, typename S, typename SX, typename T>
+__device__ __forceinline__ void hop_dir_rt(const HopArgs<S, SX>& a, int par, const Coords& c, int s, const int (&rr)[R],
+                                           T sgf, T sgb, Spinor<T> (&acc)[R]) {
+  const Geom& g = a.g;
+  const int po = 1 - par;
+  int xf = c.x, yf = c.y, zf = c.z, tf = c.t;
+  int xb = c.x, yb = c.y, zb = c.z, tb = c.t;
+  T wf = (T)1, wb = (T)1;
+  if constexpr (MU == 0) {
+    const T wrap = g.bc == BC_SF ? (T)0 : (g.bc == BC_ANTIPERIODIC ? (T)-1 : (T)1);
+    tf = c.t + 1;
+    if (tf == g.td) {
+      tf = 0;
+      wf = wrap;
+    }
+    tb = c.t - 1;
+    if (tb < 0) {
+      tb = g.td - 1;
+      wb = wrap;
+    }
+  } else if constexpr (MU == 1) {
+    xf = (c.x + 1 == g.lx) ? 0 : c.x + 1;
+    xb = (c.x == 0) ? g.lx - 1 : c.x - 1;
+  } else if constexpr (MU == 2) {
+    yf = (c.y + 1 == g.ly) ? 0 : c.y + 1;
+    yb = (c.y == 0) ? g.ly - 1 : c.y - 1;
+  } else {
+    zf = (c.z + 1 == g.lz) ? 0 : c.z + 1;
+    zb = (c.z == 0) ? g.lz - 1 : c.z - 1;
+  }
+  const int sf = half_index(g, xf, yf, zf, tf);
+  const int sbk = half_index(g, xb, yb, zb, tb);
+  cpx<T> u[9];
+  load_link(a.links, par, MU, s, u);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {  // forward: (1 + sgf g_mu) U_mu(n) psi(n + mu)
+    Spinor<T> nb;
+    load_spinor(a.in, rr[q], po, sf, nb);
+    cpx<T> h0[3], h1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) project<MU>(nb, sgf, k, h0[k], h1[k]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const cpx<T> g0 = cmul(u[3 * i], h0[0]) + cmul(u[3 * i + 1], h0[1]) + cmul(u[3 * i + 2], h0[2]);
+      const cpx<T> g1 = cmul(u[3 * i], h1[0]) + cmul(u[3 * i + 1], h1[1]) + cmul(u[3 * i + 2], h1[2]);
+      reconstruct<MU>(acc[q], sgf, i, wf * g0, wf * g1);
+    }
+  }
+  load_link(a.links, po, MU, sbk, u);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {  // backward: U_mu(n - mu)^+ psi(n - mu)
+    Spinor<T> nb;
+    load_spinor(a.in, rr[q], po, sbk, nb);
+    cpx<T> h0[3], h1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) project<MU>(nb, sgb, k, h0[k], h1[k]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const cpx<T> g0 = cjmul(u[i], h0[0]) + cjmul(u[3 + i], h0[1]) + cjmul(u[6 + i], h0[2]);
+      const cpx<T> g1 = cjmul(u[i], h1[0]) + cjmul(u[3 + i], h1[1]) + cjmul(u[6 + i], h1[2]);
+      reconstruct<MU>(acc[q], sgb, i, wb * g0, wb * g1);
+    }
+  }
+}
+
+template <int EPI, int R, typename S, typename SX>
+__global__ __launch_bounds__(256) void hop_rt_kernel(HopArgs<S, SX> a) {
+  using T = typename Compute<S>::T;
+  const int tile = tile_index(a.xcd);
+  int par = a.par;
+  int s0;
+  if (par == 2) {
+    par = tile & 1;
+    s0 = tile_site0(a, tile >> 1, blockDim.x);
+  } else {
+    s0 = tile_site0(a, tile, blockDim.x);
+  }
+  const int s = s0 + threadIdx.x;
+  const int r0 = blockIdx.y * R;
+  int rr[R];
+  bool live[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = r0 + q;
+    rr[q] = r < a.n_rhs ? r : a.n_rhs - 1;
+    bool on = r < a.n_rhs;
+    if (on && a.sc) on = a.upd_mode >= 0 ? in_update(a.sc[r], a.upd_mode) : a.sc[r].state < a.skip_state;
+    live[q] = on;
+  }
+  // the fused CG step length: wave 0 reduces the |D p|^2 partials of every
+  // RHS of the group (loads issued here, reduced after the hopping term)
+  __shared__ double s_alpha[R];
+  double av[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) av[q] = 0.0;
+  if constexpr (EPI == EPI_CGUPD) {
+    if (a.apart && threadIdx.x < 64)
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        for (int j = threadIdx.x; j < a.anblk; j += 64) av[q] += a.apart[(long)rr[q] * a.anblk + j];
+  }
+  const bool site_ok = s < a.g.vh;
+  Spinor<T> acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) zero(acc[q]);
+  if (site_ok) {
+    const Coords c = site_coords(a.g, s, par);
+    const T sgf = a.dagger ? (T)1 : (T)-1;
+    const T sgb = -sgf;
+    hop_dir_rt<0, R>(a, par, c, s, rr, sgf, sgb, acc);
+    hop_dir_rt<1, R>(a, par, c, s, rr, sgf, sgb, acc);
+    hop_dir_rt<2, R>(a, par, c, s, rr, sgf, sgb, acc);
+    hop_dir_rt<3, R>(a, par, c, s, rr, sgf, sgb, acc);
+  }
+  double alpha[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) alpha[q] = 0.0;
+  if constexpr (EPI == EPI_CGUPD) {
+    if (a.apart) {
+      if (threadIdx.x < 64) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double v = wave_sum(av[q]);
+          if (threadIdx.x == 0) {
+            double al = 0.0;
+            const int r = r0 + q;
+            if (r < a.n_rhs && a.sc[r].state == ST_ACTIVE) {
+              if (isfinite(v) && v > 0.0) al = a.sc[r].rho / v;
+              else if (blockIdx.x == 0) a.sc[r].state = ST_CHECK;
+            }
+            s_alpha[q] = al;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < R; ++q) alpha[q] = s_alpha[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) alpha[q] = r0 + q < a.n_rhs ? a.sc[r0 + q].alpha : 0.0;
+    }
+  }
+  double red[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) red[q] = (site_ok && live[q]) ? hop_epilogue<EPI>(a, par, s, rr[q], alpha[q], acc[q]) : 0.0;
+  if (a.part) {
+    __shared__ double ws[R][4];
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double v = wave_sum(red[q]);
+      if ((threadIdx.x & 63) == 0) ws[q][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+      const int q = threadIdx.x;
+      double t = 0.0;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += ws[q][k];
+      if (r0 + q < a.n_rhs) a.part[(long)(r0 + q) * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
 Shape default_shape(int n_rhs) {
   Shape sh;
   sh.xcd = 0;
@@ -288,7 +458,7 @@ int max_hop_blocks(const Geom& g) {
 template <typename S, typename SX>
 hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st) {
   HopArgs<S, SX> b = a;
-  b.xcd = sh.xcd & 1;  // bit 1: z-blocked order (below); bit 2: LDS link tile (plain kernel)
+  b.xcd = sh.xcd & 1;  // bit 1: z-blocked order (below); bit 2: LDS link tile (plain kernel); bit 3: RHS in the thread
   b.zb = 0;
   b.tpp = 0;
   {
@@ -327,6 +497,31 @@ hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st
     }
 #undef MFQ_SPLIT
     return hipGetLastError();
+  }
+  if constexpr (sizeof(S) != 8) {
+    if ((sh.xcd & 8) && sh.tc == 0) {
+      // RHS in the thread: sh.nr RHS per thread, sh.sb sites per workgroup
+      const dim3 grid(hop_grid_x(a.g, sh, a.par), (a.n_rhs + sh.nr - 1) / sh.nr), block(sh.sb);
+#define MFQ_RT(E, R) hipLaunchKernelGGL((hop_rt_kernel<E, R, S, SX>), grid, block, 0, st, b)
+#define MFQ_RT_N(E)                    \
+  switch (sh.nr) {                     \
+    case 2: MFQ_RT(E, 2); break;       \
+    case 3: MFQ_RT(E, 3); break;       \
+    case 4: MFQ_RT(E, 4); break;       \
+    case 5: MFQ_RT(E, 5); break;       \
+    case 8: MFQ_RT(E, 8); break;       \
+    default: return hipErrorInvalidValue; \
+  }
+      switch (epi) {
+        case EPI_HOP: MFQ_RT_N(EPI_HOP); break;
+        case EPI_D: MFQ_RT_N(EPI_D); break;
+        case EPI_CGUPD: MFQ_RT_N(EPI_CGUPD); break;
+        default: return hipErrorInvalidValue;
+      }
+#undef MFQ_RT_N
+#undef MFQ_RT
+      return hipGetLastError();
+    }
   }
   dim3 block(sh.sb, sh.nr);
   dim3 grid(hop_grid_x(a.g, sh, a.par), (a.n_rhs + sh.nr - 1) / sh.nr);
@@ -433,11 +628,12 @@ hipError_t launch_finish(int fin, const Partials* parts, int n_parts, int n_rhs,
 }
 
 // --------------------------------------------------------- vector kernels
-// Lanes cover both parities: q in [0, 2 vh), parity q / vh, site q % vh.
+// Lanes cover both parities (or the even one, npar = 1): q in [0, npar vh),
+// parity q / vh, site q % vh.
 #define MFQ_FULL_LANE                                             \
   const int q = blockIdx.x * blockDim.x + threadIdx.x;            \
   const int r = blockIdx.y * blockDim.y + threadIdx.y;            \
-  if (q >= 2 * g.vh || r >= n_rhs) return;                        \
+  if (q >= g.npar * g.vh || r >= n_rhs) return;                   \
   const int par = q >= g.vh ? 1 : 0;                              \
   const int s = q - par * g.vh;
 
@@ -519,7 +715,7 @@ __global__ void norm2_kernel(Geom g, Field<double> f, double* part, int n_rhs) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
   double v = 0.0;
-  if (q < 2 * g.vh && r < n_rhs) {
+  if (q < g.npar * g.vh && r < n_rhs) {
     const int par = q >= g.vh ? 1 : 0;
     Spinor<double> a;
     load_spinor(f, r, par, q - par * g.vh, a);
@@ -532,7 +728,7 @@ __global__ void init_residual_kernel(Geom g, Field<double> b, Field<double> r64,
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y * blockDim.y + threadIdx.y;
   double v = 0.0;
-  if (q < 2 * g.vh && r < n_rhs) {
+  if (q < g.npar * g.vh && r < n_rhs) {
     const int par = q >= g.vh ? 1 : 0;
     Spinor<double> a;
     load_spinor(b, r, par, q - par * g.vh, a);
@@ -577,7 +773,7 @@ template hipError_t launch_zero_parity<float>(const Geom&, Field<float>, int, in
 template hipError_t launch_zero_parity<_Float16>(const Geom&, Field<_Float16>, int, int, hipStream_t);
 
 static inline dim3 full_grid(const Geom& g, Shape sh, int n_rhs) {
-  return dim3((2 * g.vh + sh.sb - 1) / sh.sb, (n_rhs + sh.nr - 1) / sh.nr);
+  return dim3((g.npar * g.vh + sh.sb - 1) / sh.sb, (n_rhs + sh.nr - 1) / sh.nr);
 }
 
 template <typename S>

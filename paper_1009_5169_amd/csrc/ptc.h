@@ -45,7 +45,7 @@ hipError_t ptc_loss_grad_out(const Geom& g, Field<float> y, Field<double> e, con
 
 // Adam on the FP32 master weights (Re and Im as separate parameters);
 // also refreshes the BF16-rounded inference copy.
-hipError_t ptc_adam(float* w, const double* grad, float* m, float* v, int n_real, int t, float lr, float b1, float b2,
-                    float eps, f2* w_infer, hipStream_t st);
+hipError_t ptc_adam(float* w, const double* grad, float* m, float* v, int n_real, int t, double lr, double b1,
+                    double b2, double eps, f2* w_infer, hipStream_t st);
 
 }  // namespace mfq

@@ -391,26 +391,33 @@ __device__ __forceinline__ float round_bf16(float f) {
   return __uint_as_float(u & 0xffff0000u);
 }
 
-__global__ void ptc_adam_kernel(float* w, const double* grad, float* m, float* v, int n_real, int t, float lr, float b1,
-                                float b2, float eps, float* w_infer) {
+// One Adam step (Kingma and Ba, Algorithm 1) on FP32 master weights, Re and Im
+// separate parameters.  The coefficients that depend only on beta and t
+// (1 - beta, 1 - beta^t) come from the host in FP64 and are rounded once:
+// forming 1 - beta in FP32 from beta = 0.999f would be off by 1.3e-5.
+__global__ void ptc_adam_kernel(float* w, const double* grad, float* m, float* v, int n_real, float lr, float b1,
+                                float c1, float b2, float c2, float inv_bc1, float inv_bc2, float eps,
+                                float* w_infer) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_real) return;
   const float gr = (float)grad[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gr;
-  const float vi = b2 * v[i] + (1.f - b2) * gr * gr;
+  const float mi = b1 * m[i] + c1 * gr;
+  const float vi = b2 * v[i] + c2 * (gr * gr);
   m[i] = mi;
   v[i] = vi;
-  const float mh = mi / (1.f - powf(b1, (float)t));
-  const float vh = vi / (1.f - powf(b2, (float)t));
+  const float mh = mi * inv_bc1;
+  const float vh = vi * inv_bc2;
   const float wi = w[i] - lr * mh / (sqrtf(vh) + eps);
   w[i] = wi;
   w_infer[i] = round_bf16(wi);
 }
 
-hipError_t ptc_adam(float* w, const double* grad, float* m, float* v, int n_real, int t, float lr, float b1, float b2,
-                    float eps, f2* w_infer, hipStream_t st) {
-  hipLaunchKernelGGL(ptc_adam_kernel, dim3((n_real + 255) / 256), dim3(256), 0, st, w, grad, m, v, n_real, t, lr, b1,
-                     b2, eps, (float*)w_infer);
+hipError_t ptc_adam(float* w, const double* grad, float* m, float* v, int n_real, int t, double lr, double b1,
+                    double b2, double eps, f2* w_infer, hipStream_t st) {
+  const double bc1 = 1.0 - pow(b1, (double)t), bc2 = 1.0 - pow(b2, (double)t);
+  hipLaunchKernelGGL(ptc_adam_kernel, dim3((n_real + 255) / 256), dim3(256), 0, st, w, grad, m, v, n_real, (float)lr,
+                     (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)(1.0 / bc1),
+                     (float)(1.0 / bc2), (float)eps, (float*)w_infer);
   return hipGetLastError();
 }
 

@@ -21,9 +21,12 @@ def workloads():
     for dims in ((8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32)):
         for n in range(1, 9):
             out.append((dims, "sf", n, "fp32"))
-    for n in (1, 5):
+    for n in (1, 5, 8):
         for prec in ("fp64", "fp32", "fp16"):
             out.append(((32, 32, 32, 64), "periodic", n, prec))
+    for n in (1, 5):
+        out.append(((48, 48, 48, 48), "periodic", n, "fp32"))
+    out.append(((32, 32, 32, 64), "sf", 5, "fp32"))
     return out
 
 

@@ -171,6 +171,14 @@ def gaussian_momenta(dims, bc, seed: int) -> np.ndarray:
     return rng.standard_normal((4, link_slices(dims, bc), lz, ly, lx, 8))
 
 
+def gaussian_momentum_matrices(dims, bc, seed: int) -> np.ndarray:
+    """The same draw as ``gaussian_momenta`` laid out as Hermitian traceless
+    matrices sum_a P^a lambda_a / 2, shape [mu][x0][z][y][x][3][3] (the
+    library's momentum layout)."""
+    pa = gaussian_momenta(dims, bc, seed)
+    return np.ascontiguousarray(np.tensordot(pa, _GELL_MANN / 2, axes=([5], [0])))
+
+
 @dataclasses.dataclass(frozen=True)
 class Problem:
     """One lattice problem: geometry, hopping parameter, link and RHS seeds."""

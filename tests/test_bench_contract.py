@@ -59,5 +59,6 @@ def test_solver_names_match_the_header():
     from paper_1009_5169_amd import _lib
     header = open(os.path.join(ROOT, "include", "mfq.h")).read()
     enum = dict((k, int(v)) for k, v in re.findall(r"MFQ_PC_(\w+)\s*=\s*(\d+)", header))
-    assert enum == {"NONE": 0, "PTC": 1, "IDENTITY": 2, "BLOCKCG": 3}
-    assert _lib.PRECOND == {"none": 0, "ptc": 1, "identity": 2, "blockcg": 3}
+    assert enum == {"NONE": 0, "PTC": 1, "IDENTITY": 2, "BLOCKCG": 3, "BICGSTAB": 4, "GL_BICGSTAB": 5,
+                    "BL_BICGSTAB": 6}
+    assert {k.upper(): v for k, v in _lib.PRECOND.items()} == enum

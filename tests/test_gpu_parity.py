@@ -244,6 +244,44 @@ def test_z_blocked_tile_order_matches_oracle(tmp_path, monkeypatch, lattice, sha
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("shape,lattice", [
+    ((64, 3, 8, 0, 0), ((4, 6, 2, 10), "sf")), ((128, 2, 9, 0, 0), ((4, 6, 2, 10), "sf")),
+    ((256, 3, 8, 0, 0), ((6, 2, 4, 6), "periodic")), ((64, 2, 11, 0, 0), ((8, 16, 6, 6), "sf")),
+    ((64, 3, 10, 0, 0), ((8, 16, 4, 4), "periodic"))],
+    ids=lambda v: "sb%d_nr%d_xcd%d_tc%d_ds%d" % v if len(v) == 5 else f"{v[1]}{'x'.join(map(str, v[0]))}")
+def test_rhs_in_thread_shapes_match_oracle(tmp_path, monkeypatch, shape, lattice, prec):
+    """The RHS-in-thread hopping kernel (order flag bit 3: each thread one site
+    for nr RHS, links loaded once per thread), forced through the tuning cache:
+    groups of 2 over 3 RHS (a ragged last group), workgroups of 64..256 sites,
+    with the XCD remap and the z-blocked order.  Solutions meet the oracle's
+    residual and error bound."""
+    dims, bc = lattice
+    kappa, n, tol = 0.13, 3, 1e-10
+    key = "gfx950 %d %d %d %d %d %d %d" % (dims + (BC_CODE[bc], n, PREC_BYTES[prec]))
+    cache = tmp_path / "tune.txt"
+    cache.write_text(key + "|%d %d %d %d %d\n" % shape)
+    monkeypatch.setenv("MFQ_AUTOTUNE_CACHE", str(cache))
+    _, lat, d = make(dims, bc, kappa, 0.4, 1150)
+    b = synth.gaussian_spinors(dims, bc, n, 2150)
+    # the operator in the forced shape (both-parity launches), element by element
+    for op in ("D", "Ddag"):
+        got = to_host(lat.dslash(op, to_dev(b), prec=prec))
+        want = d.D(b) if op == "D" else d.Ddag(b)
+        assert rel(got, want) < (2e-6 if prec == "fp32" else 1e-2), (op, rel(got, want))
+    x, stats, rc = lat.solve(to_dev(b), tol=tol, prec=prec, max_iter=5000)
+    assert tuple(lat.hop_shape(prec, n)) == shape
+    assert rc == 0, stats
+    x = to_host(x)
+    for i in range(n):
+        res = np.linalg.norm(b[i:i + 1] - d.DdagD(x[i:i + 1])) / np.linalg.norm(b[i])
+        assert res <= tol * 1.05, (i, res)
+    x_ref, _ = solvers.cg_normal(d, b, 1e-14)
+    c = _cond(d, b)
+    assert rel(x, x_ref) <= c * (tol + 1e-14) + 1e-14, (rel(x, x_ref), c)
+    lat.close()
+
+
 @pytest.mark.parametrize("shape", [(64, 3, 4, 0, 0), (256, 2, 6, 0, 0)],
                          ids=lambda s: "sb%d_nr%d_xcd%d_tc%d_ds%d" % s)
 def test_lds_link_tile_fp16_matches_oracle(tmp_path, monkeypatch, shape):
