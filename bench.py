@@ -135,8 +135,9 @@ def main():
     ap.add_argument("--bw-dims", default="32,32,32,64")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the batch, FP16 and learned-preconditioner measurements")
-    ap.add_argument("--rows", default="fp16,learned,batch",
-                    help="which comparison rows to run (comma list of fp16, learned, batch)")
+    ap.add_argument("--rows", default="fp16,learned,batch,routes,paper_solvers,hmc",
+                    help="which comparison rows to run (comma list of fp16, learned, batch, routes, "
+                         "paper_solvers, hmc)")
     ap.add_argument("--rows-only", action="store_true",
                     help="run only the comparison rows (no bench step), for kernel traces of them")
     ap.add_argument("--profile-big", action="store_true",
@@ -188,8 +189,6 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
     # the same step once more (untimed), keeping X and Y for the oracle comparison
     g_step, action_step, stats_step, _, x_step, y_step = lat.force(phi, params=params, want_xy=True)
-    print("[bench] oracle reference for the bench workload", file=sys.stderr, flush=True)
-    ref = oracle_config1(p, u, phi_h, np)
 
     # dominant kernel: the fused hopping kernel with the D epilogue of the inner
     # CG (both parities in one launch), same launch shape as in the solve,
@@ -228,7 +227,11 @@ def main():
     sb_ms, xb, stb = solve_ms("fp64", precond="blockcg")  # one Krylov space for all RHS
     x64h = x64.cpu().numpy()
     err = lambda a: float(np.linalg.norm(a.cpu().numpy() - x64h) / np.linalg.norm(x64h))
-    err_o = lambda a: rel_err(a.cpu().numpy(), ref["z"], np)
+    # results the CPU-baseline leg compares with the oracle
+    gpu_results = {"g": g_step.cpu().numpy(), "x": x_step.cpu().numpy(), "y": y_step.cpu().numpy(),
+                   "s": list(action_step),
+                   "z": {args.prec: x_this.cpu().numpy(), "fp64": x64h, "fp16": x16.cpu().numpy(),
+                         "block_cg_fp64": xb.cpu().numpy()}}
 
     out = {
         "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms", "n_gpus": 1,
@@ -246,15 +249,6 @@ def main():
         "iters": {args.prec: [s["iters"] for s in st_this], "fp64": [s["iters"] for s in st64],
                   "fp16": [s["iters"] for s in st16], "block_cg_fp64": [s["iters"] for s in stb]},
         "solution_rel_err_vs_fp64_path": {args.prec: err(x_this), "fp16": err(x16), "block_cg_fp64": err(xb)},
-        "rel_err_vs_oracle": {
-            "step": {"force": rel_err(g_step.cpu().numpy(), ref["g"], np),
-                     "X": rel_err(x_step.cpu().numpy(), ref["x"], np),
-                     "Y": rel_err(y_step.cpu().numpy(), ref["y"], np),
-                     "action": float(max(abs(a - b) / b for a, b in zip(action_step, ref["s"])))},
-            "solve": {args.prec: err_o(x_this), "fp64": err_o(x64), "fp16": err_o(x16),
-                      "block_cg_fp64": err_o(xb)},
-            "oracle": "FP64 CPU oracle: per-RHS CG to 1e-13 (Alg. 2's two solves for X, Y; the normal "
-                      "equations for the solve rows), literal per-generator force"},
         "true_rel_resid_max": max(s["true_rel_resid"] for s in st_this),
     }
 
@@ -269,13 +263,36 @@ def main():
                 "workload": "32^3x64 periodic, 5 RHS (HBM-resident: 2.4 GB per launch)",
                 "shape": main_run["shape"]}
 
+    row_results = {}
     if not args.no_rows:
-        out["rows"] = run_rows(args, synth, mfq, torch, dev, np)
+        out["rows"] = run_rows(args, synth, mfq, torch, dev, np, row_results)
 
     if not args.no_cpu_baseline:
+        # the CPU-baseline leg: the oracle timed on the host, and the oracle's
+        # results that every GPU result above is compared with
         out["cpu_baseline"] = cpu_baseline(p, u, phi_h, np)
+        out["rel_err_vs_oracle"] = oracle_errors(p, u, phi_h, gpu_results, row_results, synth, np)
     lat.close()
     print(json.dumps(out))
+
+
+def oracle_errors(p, u, phi_h, gpu, rows, synth, np):
+    """Errors of the GPU results against the FP64 oracle (part of the
+    CPU-baseline leg; the oracle's solves are untimed here)."""
+    print("[bench] oracle reference for the bench workload", file=sys.stderr, flush=True)
+    ref = oracle_config1(p, u, phi_h, np)
+    out = {"oracle": "FP64 CPU oracle: per-RHS CG to 1e-13 (Alg. 2's two solves for X, Y; the normal "
+                     "equations for the solve rows), literal per-generator force; 16^3x16 rows: the first "
+                     "RHS, CG to 1e-12",
+           "step": {"force": rel_err(gpu["g"], ref["g"], np), "X": rel_err(gpu["x"], ref["x"], np),
+                    "Y": rel_err(gpu["y"], ref["y"], np),
+                    "action": float(max(abs(a - b) / b for a, b in zip(gpu["s"], ref["s"])))},
+           "solve": {k: rel_err(v, ref["z"], np) for k, v in gpu["z"].items()}}
+    for row, (q, xs) in rows.items():
+        print(f"[bench] oracle CG (first RHS) for row {row}", file=sys.stderr, flush=True)
+        x_or = oracle_first_rhs(q, q.links(), q.rhs())
+        out[row] = {k: rel_err(v[:1], x_or, np) for k, v in xs.items()}
+    return out
 
 
 def cpu_baseline(p, u, phi_h, np):
@@ -355,16 +372,24 @@ def bandwidth_runs(args, synth, mfq, torch, dev, np):
     return out
 
 
-def run_rows(args, synth, mfq, torch, dev, np):
-    """The comparison rows named by --rows."""
+def run_rows(args, synth, mfq, torch, dev, np, row_results=None):
+    """The comparison rows named by --rows; row_results (if given) receives
+    each 16^3x16 row's solutions for the oracle comparison."""
     rows = set(args.rows.split(","))
     out = {}
+    keep = row_results if row_results is not None else {}
     if "fp16" in rows:
-        out["fp16_16x16x16x16"] = bench_fp16(synth, mfq, torch, dev, np)
+        out["fp16_16x16x16x16"] = bench_fp16(synth, mfq, torch, dev, np, keep)
     if "learned" in rows:
-        out["learned_16x16x16x16"] = bench_learned(synth, mfq, torch, dev, np)
+        out["learned_16x16x16x16"] = bench_learned(synth, mfq, torch, dev, np, keep)
     if "batch" in rows:
         out["batch_64_lattices"] = bench_batch(synth, mfq, torch, dev, np)
+    if "routes" in rows:
+        out["routes"] = bench_routes(synth, mfq, torch, dev, np)
+    if "paper_solvers" in rows:
+        out["paper_solvers_16x16x16x16"] = bench_paper_solvers(synth, mfq, torch, dev, np)
+    if "hmc" in rows:
+        out["hmc_8x8x8x8"] = bench_hmc(synth, mfq, torch, dev, np)
     return out
 
 
@@ -379,7 +404,7 @@ def _timed(fn, reps=3):
     return (time.perf_counter() - t) * 1e3 / reps, res
 
 
-def bench_fp16(synth, mfq, torch, dev, np):
+def bench_fp16(synth, mfq, torch, dev, np, keep):
     """16^3x16 SF, eps = 0.5, kappa = 0.135, 5 RHS: FP16 storage (per-site norm)
     with FP64 defect correction against FP32 and plain FP64 CG, and FP64 block
     CG (one Krylov space for the 5 RHS), all to 1e-10."""
@@ -397,10 +422,6 @@ def bench_fp16(synth, mfq, torch, dev, np):
                      "true_rel_resid_max": max(s["true_rel_resid"] for s in st)}
     for prec in ("fp32", "fp16"):
         res[prec]["rel_err_vs_fp64_path"] = float(np.linalg.norm(xs[prec] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
-    print("[bench] row fp16: oracle CG for the first RHS", file=sys.stderr, flush=True)
-    x_or = oracle_first_rhs(p, p.links(), p.rhs())
-    for prec in ("fp64", "fp32", "fp16"):
-        res[prec]["rel_err_vs_oracle_rhs0"] = rel_err(xs[prec][:1], x_or, np)
     # block CG: the 5 RHS share one Krylov space (FP64)
     pr = mfq.make_params(tol=1e-10, prec="fp64", precond="blockcg", max_iter=50000)
     ms, (x, st, rc) = _timed(lambda: lat.solve(b, params=pr))
@@ -408,13 +429,14 @@ def bench_fp16(synth, mfq, torch, dev, np):
                             "true_rel_resid_max": max(s["true_rel_resid"] for s in st),
                             "rel_err_vs_fp64_path": float(np.linalg.norm(x.cpu().numpy() - xs["fp64"])
                                                           / np.linalg.norm(xs["fp64"])),
-                            "rel_err_vs_oracle_rhs0": rel_err(x.cpu().numpy()[:1], x_or, np),
                             "iteration_ratio_vs_fp64_cg": round(st[0]["iters"] / max(res["fp64"]["iters"]), 3)}
+    xs["block_cg_fp64"] = x.cpu().numpy()
+    keep["fp16_16x16x16x16"] = (p, {k: v[:1] for k, v in xs.items()})
     lat.close()
     return res
 
 
-def bench_learned(synth, mfq, torch, dev, np):
+def bench_learned(synth, mfq, torch, dev, np, keep):
     """16^3x16 SF, eps = 0.5, kappa = 0.1375, 5 evaluation RHS: train the PTC
     network on pairs from plain CG on b = A xi with known Gaussian solutions xi
     (seeds 6000+), then FGMRES(16) with it, FGMRES(16) without it and plain
@@ -448,10 +470,7 @@ def bench_learned(synth, mfq, torch, dev, np):
     ref = xs["cg_fp64"]
     for name in ("fgmres_identity", "fgmres_ptc"):
         res[name]["rel_err_vs_cg"] = float(np.linalg.norm(xs[name] - ref) / np.linalg.norm(ref))
-    print("[bench] row learned: oracle CG for the first RHS", file=sys.stderr, flush=True)
-    x_or = oracle_first_rhs(p, p.links(), p.rhs())
-    for name in ("cg_fp64", "fgmres_identity", "fgmres_ptc"):
-        res[name]["rel_err_vs_oracle_rhs0"] = rel_err(xs[name][:1], x_or, np)
+    keep["learned_16x16x16x16"] = (p, {k: v[:1] for k, v in xs.items()})
     res["ptc_iteration_gain_vs_fgmres"] = round(sum(res["fgmres_identity"]["iters"]) /
                                                 max(1, sum(res["fgmres_ptc"]["iters"])), 3)
     # time ratios against plain FP64 CG (> 1: slower than CG)
@@ -459,6 +478,104 @@ def bench_learned(synth, mfq, torch, dev, np):
     res["identity_ms_over_cg_ms"] = round(res["fgmres_identity"]["ms"] / res["cg_fp64"]["ms"], 3)
     lat.close()
     return res
+
+
+def bench_routes(synth, mfq, torch, dev, np):
+    """Route F (one CG on D^+D over every site, then X = D^+ Y) against route S
+    (D X = Phi and D^+ Y = X, each by CG on the even/odd Schur complement) for
+    the blocked force on the 8^3x8 and 16^3x16 workloads, FP64 and FP32
+    inner, to 1e-10; and the even/odd action variant (one CG on D^+D^ over the
+    even sites).  Forces are compared with the route F force of the same
+    precision (the two routes compute the same definition)."""
+    res = {}
+    for p in (synth.CONFIG_1, synth.CONFIG_2):
+        print(f"[bench] row routes {p.name}", file=sys.stderr, flush=True)
+        lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
+        phi = torch.from_numpy(p.rhs()).to(dev)
+        row = {"workload": p.name, "tol": 1e-10}
+        for prec in ("fp64", "fp32"):
+            gs = {}
+            for route in ("full", "schur"):
+                pr = mfq.make_params(tol=1e-10, prec=prec, max_iter=50000, route=route)
+                ms, (g, act, st, rc) = _timed(lambda: lat.force(phi, params=pr), reps=3)
+                gs[route] = g.cpu().numpy()
+                row[f"{route}_{prec}"] = {"force_ms": round(ms, 3), "rc": rc, "iters": [s["iters"] for s in st]}
+            row[f"schur_{prec}"]["force_rel_diff_vs_full"] = rel_err(gs["schur"], gs["full"], np)
+            row[f"schur_{prec}"]["speedup_vs_full"] = round(row[f"full_{prec}"]["force_ms"]
+                                                            / row[f"schur_{prec}"]["force_ms"], 3)
+            pr = mfq.make_params(tol=1e-10, prec=prec, max_iter=50000)
+            ms, (g, act, st, rc) = _timed(lambda: lat.force(phi, params=pr, eo_action=True), reps=3)
+            row[f"eo_action_{prec}"] = {"force_ms": round(ms, 3), "rc": rc, "iters": [s["iters"] for s in st],
+                                        "note": "the even/odd action variant: a different action, one CG"}
+        lat.close()
+        res[p.name] = row
+    return res
+
+
+def bench_paper_solvers(synth, mfq, torch, dev, np):
+    """The paper's solver family (Sec. 3.1-3.2) on the paper's lattice shape
+    (16^3x16 SF, 5 pseudo-fermions; synthetic links eps = 0.5, kappa = 0.135):
+    Alg. 2's two solves (D X = Phi, D^+ Y = X) with BiCGStab per RHS, Global
+    BiCGStab and Block BiCGStab in FP64 (the paper's cases A, B, C) and with
+    the FP32 inner BiCGStab as preconditioner (case D1 and its block form), to
+    1e-10 on the even system; against CG on D^+D (route F).  Iterations are
+    outer iterations per solve (each applies D^ twice, or the inner solve twice)."""
+    p = synth.CONFIG_2
+    print(f"[bench] row paper solvers {p.name}", file=sys.stderr, flush=True)
+    u = p.links()
+    lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(u).to(dev))
+    phi = torch.from_numpy(p.rhs()).to(dev)
+    res = {"workload": p.name, "tol": 1e-10}
+    ref = None
+    for name, kw in (("cg_fp64_route_f", dict(prec="fp64")),
+                     ("A_bicgstab_fp64", dict(prec="fp64", precond="bicgstab")),
+                     ("B_gl_bicgstab_fp64", dict(prec="fp64", precond="gl_bicgstab")),
+                     ("C_bl_bicgstab_fp64", dict(prec="fp64", precond="bl_bicgstab")),
+                     ("D1_gl_bicgstab_fp64_fp32_inner", dict(prec="fp32", precond="gl_bicgstab")),
+                     ("bl_bicgstab_fp64_fp32_inner", dict(prec="fp32", precond="bl_bicgstab")),
+                     ("bicgstab_fp64_fp32_inner", dict(prec="fp32", precond="bicgstab"))):
+        pr = mfq.make_params(tol=1e-10, max_iter=20000, **kw)
+        ms, (g, act, st, rc, x, y) = _timed(lambda: lat.force(phi, params=pr, want_xy=True), reps=2)
+        gh = g.cpu().numpy()
+        if ref is None:
+            ref = gh
+        res[name] = {"force_ms": round(ms, 3), "rc": rc, "iters": [s["iters"] for s in st],
+                     "inner_iters": st[0]["inner_iters"], "inner_calls": st[0]["inner_calls"],
+                     "force_rel_diff_vs_cg": rel_err(gh, ref, np)}
+    a_it = max(res["A_bicgstab_fp64"]["iters"])
+    res["block_iterations_vs_per_rhs"] = {
+        "gl": round(max(res["B_gl_bicgstab_fp64"]["iters"]) / a_it, 3),
+        "bl": round(max(res["C_bl_bicgstab_fp64"]["iters"]) / a_it, 3),
+        "paper_bl_vs_per_rhs": 0.82, "note": "the paper's Bl-BiCGStab took 18% fewer iterations than the "
+                                             "sequential BiCGStab on its thermalized 16^4 configuration"}
+    lat.close()
+    return res
+
+
+def bench_hmc(synth, mfq, torch, dev, np):
+    """One leapfrog HMC trajectory on the GPU (tau = 0.5, 10 steps, 11 force
+    evaluations) on the 8^3x8 SF 5-pseudo-fermion workload with FP32 inner
+    solves to 1e-10: time per trajectory, Delta H (FP64) and the decision with
+    the draw u = 0.5.  The pseudo-fermion action only (no gauge action)."""
+    p = synth.CONFIG_1
+    print(f"[bench] row hmc {p.name}", file=sys.stderr, flush=True)
+    u = p.links()
+    lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(u).to(dev))
+    phi = torch.from_numpy(p.rhs()).to(dev)
+    # momenta on every link: the library moves only the links that enter D
+    pm = synth.gaussian_momentum_matrices(p.dims, p.bc, 4001)
+    out = {"workload": p.name, "tau": 0.5, "n_steps": 10}
+    for prec in ("fp64", "fp32"):
+        links = torch.from_numpy(u).to(dev)
+        mom = torch.from_numpy(pm).to(dev)
+        lat.update_links(links)
+        t = time.perf_counter()
+        r, rc = lat.hmc_trajectory(links, mom, phi, 0.5, 10, 0.5, tol=1e-10, prec=prec)
+        torch.cuda.synchronize()
+        out[prec] = {"ms": round((time.perf_counter() - t) * 1e3, 2), "rc": rc, "delta_h": r["delta_h"],
+                     "accepted": r["accepted"], "solver_iters": r["solver_iters"], "force_evals": r["force_evals"]}
+    lat.close()
+    return out
 
 
 def bench_batch(synth, mfq, torch, dev, np):
