@@ -194,6 +194,20 @@ int mfq_update_links(mfq_handle* h, const double* links_dev, void* stream);
 /* out = op(in) for n_rhs canonical spinors, computed in FP64.  Asynchronous. */
 int mfq_dslash(mfq_handle* h, int op, const double* in_dev, double* out_dev, int n_rhs, void* stream);
 
+/* mfq_dslash (FP64, every mfq_op) without any device allocation, for
+ * callers that cannot allocate (code under stream capture, serving loops
+ * that forbid hipMalloc).  The packed input, output and (for DDAGD) the
+ * intermediate field live in a fixed 64 MiB per-device workspace inside the
+ * library instead of the handle's workspaces; the handle's packed links are
+ * used as they are.  Sizes: 2 (3 for DDAGD and the SCHUR ops) packed fields of
+ * n_rhs * 2 * 12 * vs * 16 bytes, vs ~ (sites per parity rounded up to an odd
+ * multiple of 16), must fit in 64 MiB, else MFQ_ERR_ARG and nothing is
+ * written (for example an 8^3x8 SF lattice takes up to 18 RHS).  Results
+ * equal mfq_dslash's to rounding.  Asynchronous on `stream`.  Every call on
+ * one GPU shares that GPU's workspace: calls that overlap in time on one GPU
+ * (different streams or threads) race and must be serialised by the caller. */
+int mfq_dslash_noalloc(mfq_handle* h, int op, const double* in_dev, double* out_dev, int n_rhs, void* stream);
+
 /* Same, with the storage/arithmetic precision of an inner solve (mfq_prec):
  * the input is rounded to that precision, the operator applied in it, and the
  * result widened back to FP64. */

@@ -77,6 +77,18 @@ class Lattice:
                                              n, _lib.stream_ptr(stream)))
         return out
 
+    def dslash_noalloc(self, op: str, psi: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """FP64 op(psi) through the entry point that allocates no device memory
+        (the caller may pass the output tensor too)."""
+        n = self._check_spinor(psi)
+        if out is None:
+            out = torch.empty_like(psi)
+        elif out.shape != psi.shape or out.dtype != psi.dtype:
+            raise ValueError("out must match psi")
+        _lib.check(_lib.lib().mfq_dslash_noalloc(self._h, OPS[op], _lib.dptr(psi), _lib.dptr(out), n,
+                                                _lib.stream_ptr(stream)))
+        return out
+
     def solve(self, b: torch.Tensor, params=None, stream=None, **kw):
         """x = (D^+D)^-1 b for all RHS at once; returns (x, [stats dicts], status).
 

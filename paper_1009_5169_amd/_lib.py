@@ -73,6 +73,7 @@ _SIGNATURES = {
     "mfq_create": ([ctypes.POINTER(_Lattice), _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "mfq_update_links": ([_P, _P, _P], ctypes.c_int),
     "mfq_dslash": ([_P, ctypes.c_int, _P, _P, ctypes.c_int, _P], ctypes.c_int),
+    "mfq_dslash_noalloc": ([_P, ctypes.c_int, _P, _P, ctypes.c_int, _P], ctypes.c_int),
     "mfq_dslash_prec": ([_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int, _P], ctypes.c_int),
     "mfq_solve_multi_rhs": ([_P, _P, _P, ctypes.c_int, ctypes.POINTER(SolveParams),
                              ctypes.POINTER(SolveStats), _P], ctypes.c_int),

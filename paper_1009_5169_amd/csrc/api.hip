@@ -929,6 +929,8 @@ int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mf
     return fail_hip(e, "hipEventCreate");
   }
   rc = pack_all_links(h, links_dev, (hipStream_t)stream);
+  // set-up of mfq_dslash_noalloc: this device's address of its workspace
+  if (!rc) rc = noalloc_init_current_device();
   if (rc) {
     mfq_destroy(h);
     return rc;

@@ -112,6 +112,8 @@ int fp64_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out);
 // the both-parity launches
 int apply_op_fp64(mfq_handle* h, int op, Field<double> in, Field<double> tmp, Field<double> out, int n_rhs,
                   Shape sh2, hipStream_t st);
+// the per-device address of the no-allocation entry point's workspace
+int noalloc_init_current_device();
 // learned preconditioner (ptc_host.hip)
 void ptc_free(mfq_handle* h);
 int ptc_apply_fields(mfq_handle* h, Field<double> in, Field<double> out, int n, hipStream_t st);
