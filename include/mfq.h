@@ -332,6 +332,15 @@ int mfq_solve_batch(mfq_handle** hs, int n_lat, const double* const* b_dev, doub
 /* Persistent grid size chosen by the batch's autotuning (workgroups). */
 int mfq_batch_grid(mfq_batch* batch);
 
+/* Whether the inner hopping phases split each site's four directions over
+ * wavefronts (1) or run one thread per site (0), as chosen by the tuning. */
+int mfq_batch_split(mfq_batch* batch);
+
+/* Override the tuned launch shape of the persistent kernels: grid size
+ * (workgroups, 1..65536) and the direction split (0 or 1); drops the
+ * captured graphs. */
+int mfq_batch_set_shape(mfq_batch* batch, int grid, int split);
+
 void mfq_batch_destroy(mfq_batch* batch);
 
 /* ---- learned preconditioner: gauge-covariant parallel-transport network --

@@ -222,6 +222,15 @@ class Batch:
     def grid(self) -> int:
         return _lib.lib().mfq_batch_grid(self._b)
 
+    @property
+    def split(self) -> int:
+        return _lib.lib().mfq_batch_split(self._b)
+
+    def set_shape(self, grid: int, split: int):
+        """Force the persistent grid size and the direction split of the
+        inner hopping phases (otherwise chosen by the batch's tuning)."""
+        _lib.check(_lib.lib().mfq_batch_set_shape(self._b, int(grid), int(split)))
+
     def solve(self, bs, params=None, stream=None, **kw):
         """bs: list of canonical spinor tensors; returns (xs, stats per lattice, status)."""
         if len(bs) != len(self.lattices):

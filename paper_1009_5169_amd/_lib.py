@@ -102,6 +102,8 @@ _SIGNATURES = {
                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats),
                          _P], ctypes.c_int),
     "mfq_batch_grid": ([_P], ctypes.c_int),
+    "mfq_batch_split": ([_P], ctypes.c_int),
+    "mfq_batch_set_shape": ([_P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "mfq_batch_destroy": ([_P], None),
     "mfq_precond_init": ([_P, ctypes.c_ulonglong, ctypes.c_double], ctypes.c_int),
     "mfq_precond_set_weights": ([_P, _P], ctypes.c_int),

@@ -96,6 +96,91 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat
   }
 }
 
+// The inner-precision hopping phases with the directions of a site split
+// over DS wavefronts (as the single-lattice direction-split kernel): the
+// tile keeps its geometry (sb sites x nr RHS rows) and is walked in DS
+// passes of 512 / DS (site, RHS) items, each pass's partial hopping terms
+// meeting in LDS, where the first wavefront of each item group applies the
+// epilogue.  Shorter dependent-load chains per thread, as in the tuned
+// kernels of the one-by-one solves.  Per-row partial sums are added in a
+// fixed order (pass, group).
+template <int MODE, int DS, typename S, typename SX>
+__global__ __launch_bounds__(kBatchThreads) void batch_hop_split_kernel(const BatchLat<S, SX>* lats,
+                                                                        const Tile* tiles, const int* n_tiles_dev,
+                                                                        int slot) {
+  using T = typename Compute<S>::T;
+  constexpr int G = kBatchThreads / 64 / DS;  // 64-item groups per pass
+  constexpr int PER_PASS = kBatchThreads / DS;
+  __shared__ T lds[G][DS - 1][24][64];
+  __shared__ double wsum[DS][G];
+  const int n_tiles = *n_tiles_dev;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = wave / DS, d = wave - grp * DS;
+  for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
+    const Tile tl = tiles[it];
+    const BatchLat<S, SX>& L = lats[tl.lat];
+    const HopArgs<S, SX>& a = MODE == BM_D ? L.d : L.cg;
+    const int par = tl.tile & 1;
+    for (int pass = 0; pass < DS; ++pass) {
+      const int item = pass * PER_PASS + grp * 64 + lane;  // a 64-item group lies in one row (sb % 64 == 0)
+      const int row = item / L.sb;
+      const int s = (tl.tile >> 1) * L.sb + (item - row * L.sb);
+      const int r = tl.rgrp * L.nr + row;
+      const bool active = s < a.g.vh && r < a.n_rhs && a.sc[r].state < a.skip_state;
+      Spinor<T> acc;
+      zero(acc);
+      if (active) {
+        const Coords c = site_coords(a.g, s, par);
+        if constexpr (DS == 2) {
+          if (d == 0) hop_dirs<0, 2>(a, par, s, c, r, acc);
+          else hop_dirs<2, 4>(a, par, s, c, r, acc);
+        } else {
+          if (d == 0) hop_dirs<0, 1>(a, par, s, c, r, acc);
+          else if (d == 1) hop_dirs<1, 2>(a, par, s, c, r, acc);
+          else if (d == 2) hop_dirs<2, 3>(a, par, s, c, r, acc);
+          else hop_dirs<3, 4>(a, par, s, c, r, acc);
+        }
+      }
+      if (d > 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          lds[grp][d - 1][2 * k][lane] = acc.v[k].re;
+          lds[grp][d - 1][2 * k + 1][lane] = acc.v[k].im;
+        }
+      }
+      __syncthreads();
+      if (d == 0) {
+        double red = 0.0;
+        if (active) {
+#pragma unroll
+          for (int q = 0; q < DS - 1; ++q)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+              acc.v[k].re += lds[grp][q][2 * k][lane];
+              acc.v[k].im += lds[grp][q][2 * k + 1][lane];
+            }
+          red = hop_epilogue<MODE == BM_D ? EPI_D : EPI_CGUPD>(a, par, s, r, a.sc[r].alpha, acc);
+        }
+        red = wave_sum(red);
+        if (lane == 0) wsum[pass][grp] = red;
+      }
+      __syncthreads();  // the next pass reuses the LDS
+    }
+    if (slot >= 0) {
+      if ((int)threadIdx.x < L.nr) {
+        const int row = threadIdx.x;
+        double t = 0.0;
+        for (int pass = 0; pass < DS; ++pass)
+          for (int g2 = 0; g2 < G; ++g2)
+            if ((pass * PER_PASS + g2 * 64) / L.sb == row) t += wsum[pass][g2];
+        const int r = tl.rgrp * L.nr + row;
+        if (r < L.n_rhs) L.part[slot][(long)r * L.nblk_both + tl.tile] = t;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <int MODE, typename S, typename SX>
 __global__ __launch_bounds__(kBatchThreads) void batch_vec_kernel(const BatchLat<S, SX>* lats, const Tile* tiles,
                                                                   const int* n_tiles_dev, int mode) {
@@ -204,6 +289,7 @@ struct mfq_batch {
   std::vector<Tile> host_th, host_tf;
   DevBuf counts;  // int[2]: current lengths of the two lists
   int grid = 512;
+  int split = 0;  // the inner hopping phases split directions over wavefronts
   CgScalars* host_sc = nullptr;
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -387,6 +473,14 @@ hipError_t bhop(mfq_batch* B, int mode, int slot, hipStream_t st, int upd_mode =
   const Tile* t = (const Tile*)B->tiles_h.ptr;
   const int grid = B->grid < B->n_tiles_h ? B->grid : B->n_tiles_h;
   const int* nt = (const int*)B->counts.ptr;
+  constexpr int DS = sizeof(typename Compute<S>::T) == 8 ? 2 : 4;  // LDS: 48 KB (FP64) / 36 KB (FP32)
+  if (B->split && (mode == BM_D || mode == BM_CG)) {
+    if (mode == BM_D)
+      hipLaunchKernelGGL((batch_hop_split_kernel<BM_D, DS, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot);
+    else
+      hipLaunchKernelGGL((batch_hop_split_kernel<BM_CG, DS, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot);
+    return hipGetLastError();
+  }
   switch (mode) {
     case BM_D: hipLaunchKernelGGL((batch_hop_kernel<BM_D, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot, upd_mode); break;
     case BM_CG: hipLaunchKernelGGL((batch_hop_kernel<BM_CG, S, SX>), grid, kBatchThreads, 0, st, L, t, nt, slot, upd_mode); break;
@@ -421,12 +515,14 @@ hipError_t bfin(mfq_batch* B, int which, int fin, double tol2, double delta2, hi
 
 template <typename S, typename SX>
 int batch_tune(mfq_batch* B, hipStream_t st) {
-  // persistent grid size: a few multiples of the 256 CUs
-  int best_grid = 512;
+  // persistent grid size (a few multiples of the 256 CUs) and whether the
+  // inner hopping phases split directions over wavefronts
+  int best_grid = 512, best_split = 0;
   float best = 1e30f;
   const int cands[4] = {256, 512, 1024, 2048};
-  for (int c = 0; c < 4; ++c) {
-    B->grid = cands[c];
+  for (int c = 0; c < 8; ++c) {
+    B->grid = cands[c & 3];
+    B->split = c >> 2;
     for (int i = 0; i < 2; ++i) HIPCHK(bhop<S, SX>(B, BM_D, -1, st));
     HIPCHK(hipEventRecord(B->ev0, st));
     for (int i = 0; i < 5; ++i) HIPCHK(bhop<S, SX>(B, BM_D, -1, st));
@@ -436,10 +532,12 @@ int batch_tune(mfq_batch* B, hipStream_t st) {
     HIPCHK(hipEventElapsedTime(&ms, B->ev0, B->ev1));
     if (ms < best * 0.97f) {
       best = ms;
-      best_grid = cands[c];
+      best_grid = cands[c & 3];
+      best_split = c >> 2;
     }
   }
   B->grid = best_grid;
+  B->split = best_split;
   return MFQ_OK;
 }
 
@@ -530,7 +628,7 @@ int batch_run(mfq_batch* B, const mfq_solve_params* P, hipStream_t st, mfq_solve
       }
       return MFQ_OK;
     }
-    std::vector<uintptr_t> key = {(uintptr_t)k, bits(tol2), bits(delta2), (uintptr_t)B->grid};
+    std::vector<uintptr_t> key = {(uintptr_t)k, bits(tol2), bits(delta2), (uintptr_t)B->grid, (uintptr_t)B->split};
     GraphEntry* hit = nullptr;
     for (auto& e : B->graphs)
       if (e.key == key) hit = &e;
@@ -738,5 +836,17 @@ int mfq_solve_batch(mfq_handle** hs, int n_lat, const double* const* b_dev, doub
 }
 
 int mfq_batch_grid(mfq_batch* B) { return B ? B->grid : -1; }
+
+int mfq_batch_set_shape(mfq_batch* B, int grid, int split) {
+  if (!B) return fail(MFQ_ERR_ARG, "NULL batch");
+  if (grid < 1 || grid > 65536 || (split != 0 && split != 1))
+    return fail(MFQ_ERR_ARG, "grid must be in 1..65536 and split 0 or 1");
+  B->grid = grid;
+  B->split = split;
+  batch_drop_graphs(B);
+  return MFQ_OK;
+}
+
+int mfq_batch_split(mfq_batch* B) { return B ? B->split : -1; }
 
 }  // extern "C"

@@ -47,14 +47,19 @@ def small_batch(seed=5000, n=7):
     return probs
 
 
+@pytest.mark.parametrize("split", [0, 1], ids=["one_thread_per_site", "direction_split"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
-def test_batch_matches_oracle_and_single_solves(prec):
+def test_batch_matches_oracle_and_single_solves(prec, split):
+    """Both forms of the persistent hopping phases (forced): one thread per
+    site, and the four directions split over wavefronts in passes."""
     probs = small_batch()
-    note(f"batch {prec}: " + ", ".join(f"{p.dims}x{p.n_rhs}" for p in probs))
+    note(f"batch {prec} split {split}: " + ", ".join(f"{p.dims}x{p.n_rhs}" for p in probs))
     links = [p.links() for p in probs]
     lats = [mfq.Lattice(p.dims, p.bc, p.kappa, to_dev(u)) for p, u in zip(probs, links)]
     rhs = [p.rhs() for p in probs]
     batch = mfq.Batch(lats, [p.n_rhs for p in probs], prec=prec)
+    batch.set_shape(batch.grid, split)
+    assert batch.split == split
     tol = 1e-10
     xs, stats, rc = batch.solve([to_dev(b) for b in rhs], tol=tol, max_iter=5000)
     note(f"grid {batch.grid}, rc {rc}, iters {[[s['iters'] for s in st] for st in stats]}, "
