@@ -312,6 +312,66 @@ __global__ __launch_bounds__(256) void ptc_wgrad_kernel(Geom g, Links<float> L, 
   }
 }
 
+// The same weight gradient with the transport moved onto the output
+// gradient: T_p^+ = T_pbar, so
+//   sum_n g(n) (T_p x)(n)^+ = sum_m (T_pbar g)(m) x(m)^+,
+// and a single-channel g (layer 2: c_out = 1) is transported once per path
+// instead of each of the c_in input channels.  blockIdx.y = path, blockIdx.z
+// a group of CI input channels; same partial layout as ptc_wgrad_kernel.
+template <typename SX, int CI>
+__global__ __launch_bounds__(256) void ptc_wgrad_adj_kernel(Geom g, Links<float> L, Field<SX> x, int c_in,
+                                                            Field<float> gf, int n_pairs, double* part) {
+  __shared__ double ws[4][CI * 32];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  const int pbar = p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4);
+  const int ci0 = blockIdx.z * CI;
+  float acc[CI][32];
+#pragma unroll
+  for (int j = 0; j < CI; ++j)
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[j][k] = 0.f;
+  if (q < 2 * g.vh) {
+    const int par = q >= g.vh ? 1 : 0;
+    const int s = q - par * g.vh;
+    const Coords c = site_coords(g, s, par);
+    for (int k = 0; k < n_pairs; ++k) {
+      Spinor<float> tg;
+      transported(g, L, gf, k, pbar, s, par, c, tg);
+#pragma unroll
+      for (int j = 0; j < CI; ++j) {
+        Spinor<float> xx;
+        load_spinor(x, k * c_in + ci0 + j, par, s, xx);
+#pragma unroll
+        for (int so = 0; so < 4; ++so)
+#pragma unroll
+          for (int si = 0; si < 4; ++si) {
+            cpx<float> o = {0.f, 0.f};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) o = o + cjmul(xx.v[3 * si + a], tg.v[3 * so + a]);
+            acc[j][2 * (4 * so + si)] += o.re;
+            acc[j][2 * (4 * so + si) + 1] += o.im;
+          }
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < CI; ++j)
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const double v = wave_sum((double)acc[j][k]);
+      if (lane == 0) ws[wave][j * 32 + k] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x < CI * 32) {
+    const int j = threadIdx.x / 32, k = threadIdx.x % 32;
+    const double v = ((ws[0][threadIdx.x] + ws[1][threadIdx.x]) + ws[2][threadIdx.x]) + ws[3][threadIdx.x];
+    const int idx = p * c_in + ci0 + j;  // (p * c_out + co) * c_in + ci with c_out = 1
+    part[((long)idx * gridDim.x + blockIdx.x) * 32 + k] = v;
+  }
+}
+
 __global__ void ptc_grad_reduce_kernel(const double* part, int nblk, int n_idx, double* grad) {
   const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // one wave per (idx, component)
   const int lane = threadIdx.x & 63;
@@ -328,7 +388,10 @@ hipError_t ptc_weight_grad(const Geom& g, Links<float> L, Field<SX> x, int c_in,
                            int n_pairs, double* part, double* grad, hipStream_t st) {
   const int nblk = (2 * g.vh + 255) / 256;
   const int n_idx = PTC_PATHS * c_in * c_out;
-  if (c_out % 4 == 0)
+  if (c_out == 1 && c_in % 4 == 0)
+    hipLaunchKernelGGL((ptc_wgrad_adj_kernel<SX, 4>), dim3(nblk, PTC_PATHS, c_in / 4), dim3(256), 0, st, g, L, x,
+                       c_in, gf, n_pairs, part);
+  else if (c_out % 4 == 0)
     hipLaunchKernelGGL((ptc_wgrad_kernel<SX, 4>), dim3(nblk, PTC_PATHS * c_in, c_out / 4), dim3(256), 0, st, g, L, x,
                        c_in, gf, c_out, n_pairs, part);
   else
