@@ -149,7 +149,8 @@ typedef enum {
  * force the two of Alg. 2 (D X = Phi, D^+ Y = X), mfq_solve_dirac one. */
 
 typedef struct {
-  int dims[4]; /* Lx, Ly, Lz, T: even, >= 2 (T >= 4 for SF)                  */
+  int dims[4]; /* Lx, Ly, Lz, T: even, >= 2 (T >= 4 for SF); volume at most
+                  4.4e7 sites and (volume / 2) * max(Lx / 2, Ly, Lz) < 2^31 */
   int bc;      /* mfq_bc                                                       */
   double kappa;/* 0 < kappa < 0.25                                             */
 } mfq_lattice;

@@ -80,7 +80,14 @@ int check_lattice(const mfq_lattice* lat) {
   if (lat->bc == MFQ_BC_SF && lat->dims[3] < 4) return fail(MFQ_ERR_ARG, "SF lattices need T >= 4");
   if (!(lat->kappa > 0.0 && lat->kappa < 0.25)) return fail(MFQ_ERR_ARG, "kappa must be in (0, 0.25)");
   const long vol = (long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
-  if (vol > (1L << 28)) return fail(MFQ_ERR_ARG, "lattice volume too large");
+  // one (RHS, parity) FP64 field (192 bytes per site) is read through one
+  // buffer resource, whose extent is below 4 GiB
+  if (vol > 44000000L) return fail(MFQ_ERR_ARG, "lattice volume too large (at most 4.4e7 sites)");
+  // site coordinates use division by multiplication, exact while n * d < 2^31
+  long dmax = lat->dims[0] / 2;
+  if (lat->dims[1] > dmax) dmax = lat->dims[1];
+  if (lat->dims[2] > dmax) dmax = lat->dims[2];
+  if (vol / 2 * dmax >= (1L << 31)) return fail(MFQ_ERR_ARG, "lattice too large: (volume / 2) * max(Lx / 2, Ly, Lz) must be < 2^31");
   return MFQ_OK;
 }
 
@@ -906,9 +913,8 @@ int mfq_create(const mfq_lattice* lat, const double* links_dev, void* stream, mf
   g.bc = lat->bc;
   g.td = lat->bc == MFQ_BC_SF ? lat->dims[3] - 1 : lat->dims[3];
   g.t0 = lat->bc == MFQ_BC_SF ? 1 : 0;
-  g.lxh = g.lx / 2;
   g.npar = 2;
-  g.vh = g.lxh * g.ly * g.lz * g.td;
+  geom_init(g);
   {
     int gr = (g.vh + 15) / 16;  // 256-byte granules of a 16-byte-per-site array
     if (gr % 2 == 0) gr += 1;

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_kernel(const BatchLat
   for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
     const Tile tl = tiles[it];
     const BatchLat<S, SX>& L = lats[tl.lat];
-    const int row = threadIdx.x / L.sb;
+    const int row = wave_uniform(threadIdx.x / L.sb);  // L.sb is a multiple of 64
     const int par = tl.tile & 1;
     const int s = (tl.tile >> 1) * L.sb + (threadIdx.x - row * L.sb);
     const int r = tl.rgrp * L.nr + row;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_split_kernel(const Ba
   __shared__ T lds[G][DS - 1][24][64];
   __shared__ double wsum[DS][G];
   const int n_tiles = *n_tiles_dev;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int grp = wave / DS, d = wave - grp * DS;
   for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
     const Tile tl = tiles[it];
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_hop_split_kernel(const Ba
     const int par = tl.tile & 1;
     for (int pass = 0; pass < DS; ++pass) {
       const int item = pass * PER_PASS + grp * 64 + lane;  // a 64-item group lies in one row (sb % 64 == 0)
-      const int row = item / L.sb;
+      const int row = wave_uniform(item / L.sb);
       const int s = (tl.tile >> 1) * L.sb + (item - row * L.sb);
       const int r = tl.rgrp * L.nr + row;
       const bool active = s < a.g.vh && r < a.n_rhs && a.sc[r].state < a.skip_state;

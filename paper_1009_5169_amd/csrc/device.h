@@ -83,7 +83,33 @@ struct Geom {
   // Parities the vector kernels cover: 2 (every site), or 1 (the even sites
   // only: the even/odd Schur-complement solves).
   int npar;
+  // Division by lxh, ly, lz without a divide: q = umulhi(2n, m) with
+  // m = ceil(2^31 / d) equals n / d whenever n * d < 2^31 (set by geom_init).
+  unsigned mxh, my, mz;
+  // Half-index strides of y, z and t, and the jumps of a periodic wrap.
+  int sy, sz, st;
+  int wy, wz, wt;  // (ly - 1) sy, (lz - 1) sz, (td - 1) st
 };
+
+// n / d for the divisors of Geom (n * d < 2^31), and the remainder.
+__device__ __forceinline__ int fdiv(int n, unsigned m) { return (int)__umulhi(2u * (unsigned)n, m); }
+
+inline unsigned fdiv_magic(int d) { return (unsigned)(((1ull << 31) + (unsigned)d - 1) / (unsigned)d); }
+
+// Fills the derived fields of g from lx, ly, lz, td.
+inline void geom_init(Geom& g) {
+  g.lxh = g.lx / 2;
+  g.vh = g.lxh * g.ly * g.lz * g.td;
+  g.mxh = fdiv_magic(g.lxh);
+  g.my = fdiv_magic(g.ly);
+  g.mz = fdiv_magic(g.lz);
+  g.sy = g.lxh;
+  g.sz = g.lxh * g.ly;
+  g.st = g.sz * g.lz;
+  g.wy = (g.ly - 1) * g.sy;
+  g.wz = (g.lz - 1) * g.sz;
+  g.wt = (g.td - 1) * g.st;
+}
 
 struct Coords {
   int x, y, z, t;
@@ -91,12 +117,12 @@ struct Coords {
 
 __device__ __forceinline__ Coords site_coords(const Geom& g, int s, int parity) {
   Coords c;
-  int xh = s % g.lxh;
-  int r = s / g.lxh;
-  c.y = r % g.ly;
-  r /= g.ly;
-  c.z = r % g.lz;
-  c.t = r / g.lz;
+  int r = fdiv(s, g.mxh);
+  const int xh = s - r * g.lxh;
+  int q = fdiv(r, g.my);
+  c.y = r - q * g.ly;
+  c.t = fdiv(q, g.mz);
+  c.z = q - c.t * g.lz;
   c.x = 2 * xh + ((c.t + g.t0 + c.y + c.z + parity) & 1);
   return c;
 }
@@ -140,7 +166,24 @@ struct Field {
   __device__ __forceinline__ long nidx(int rhs, int par, int s) const {
     return (long)(rhs * 2 + par) * vh + s;
   }
+  // Start of component array c of (rhs, par).  When rhs and par are uniform
+  // over the wavefront this is a scalar address, and an element is reached
+  // with a 32-bit per-lane byte offset (see at()).
+  __device__ __forceinline__ typename Store<S>::chunk* comp(int rhs, int par, int c) const {
+    return data + (long)((rhs * 2 + par) * Store<S>::NC + c) * vh;
+  }
 };
+
+// Element s of an array that starts at base: scalar base + 32-bit lane offset
+// (s < 2^27, so the byte offset fits in 32 bits).
+template <typename C>
+__device__ __forceinline__ C& at(C* base, int s) {
+  return *(C*)((char*)base + (unsigned)s * (unsigned)sizeof(C));
+}
+template <typename C>
+__device__ __forceinline__ const C& at(const C* base, int s) {
+  return *(const C*)((const char*)base + (unsigned)s * (unsigned)sizeof(C));
+}
 
 // Links of one precision.  FP64: full layout [parity][mu][9][site], one
 // complex per element.  FP32 and FP16 (the inner-solver copies, SU(3) links
@@ -159,17 +202,11 @@ struct Links {
   __device__ __forceinline__ long cidx(int par, int mu, int c, int s) const {
     return ((long)(par * 4 + mu) * 3 + c) * vh + s;
   }
+  __device__ __forceinline__ const typename Store<S>::link_elem* row(int par, int mu, int k) const {
+    return data + (long)((par * 4 + mu) * 9 + k) * vh;
+  }
 };
 
-template <typename T>
-__device__ __forceinline__ void third_row(cpx<T> u[9]) {
-  u[6] = {u[1].re * u[5].re - u[1].im * u[5].im - (u[2].re * u[4].re - u[2].im * u[4].im),
-          -(u[1].re * u[5].im + u[1].im * u[5].re - (u[2].re * u[4].im + u[2].im * u[4].re))};
-  u[7] = {u[2].re * u[3].re - u[2].im * u[3].im - (u[0].re * u[5].re - u[0].im * u[5].im),
-          -(u[2].re * u[3].im + u[2].im * u[3].re - (u[0].re * u[5].im + u[0].im * u[5].re))};
-  u[8] = {u[0].re * u[4].re - u[0].im * u[4].im - (u[1].re * u[3].re - u[1].im * u[3].im),
-          -(u[0].re * u[4].im + u[0].im * u[4].re - (u[1].re * u[3].im + u[1].im * u[3].re))};
-}
 
 // Spinor register block: v[3 * spin + colour].
 template <typename T>
@@ -181,7 +218,7 @@ template <typename T>
 __device__ __forceinline__ void load_spinor(const Field<double>& f, int rhs, int par, int s, Spinor<T>& o) {
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    d2 q = f.data[f.cidx(rhs, par, c, s)];
+    d2 q = at(f.comp(rhs, par, c), s);
     o.v[c] = {(T)q.x, (T)q.y};
   }
 }
@@ -189,17 +226,30 @@ template <typename T>
 __device__ __forceinline__ void load_spinor(const Field<float>& f, int rhs, int par, int s, Spinor<T>& o) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    f4 q = f.data[f.cidx(rhs, par, c, s)];
+    f4 q = at(f.comp(rhs, par, c), s);
     o.v[2 * c] = {(T)q.x, (T)q.y};
     o.v[2 * c + 1] = {(T)q.z, (T)q.w};
   }
 }
+// FP16 storage without its per-site norm: the caller applies the norm.
 template <typename T>
-__device__ __forceinline__ void load_spinor(const Field<_Float16>& f, int rhs, int par, int s, Spinor<T>& o) {
-  const float n = f.norm[f.nidx(rhs, par, s)];
+__device__ __forceinline__ void load_spinor_raw(const Field<_Float16>& f, int rhs, int par, int s, Spinor<T>& o) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    h8 q = f.data[f.cidx(rhs, par, c, s)];
+    h8 q = at(f.comp(rhs, par, c), s);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o.v[4 * c + k] = {(T)(float)q[2 * k], (T)(float)q[2 * k + 1]};
+  }
+}
+__device__ __forceinline__ float load_norm(const Field<_Float16>& f, int rhs, int par, int s) {
+  return at(f.norm + (long)(rhs * 2 + par) * f.vh, s);
+}
+template <typename T>
+__device__ __forceinline__ void load_spinor(const Field<_Float16>& f, int rhs, int par, int s, Spinor<T>& o) {
+  const float n = load_norm(f, rhs, par, s);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h8 q = at(f.comp(rhs, par, c), s);
 #pragma unroll
     for (int k = 0; k < 4; ++k) o.v[4 * c + k] = {(T)((float)q[2 * k] * n), (T)((float)q[2 * k + 1] * n)};
   }
@@ -212,7 +262,7 @@ __device__ __forceinline__ void store_spinor(const Field<double>& f, int rhs, in
     d2 q;
     q.x = (double)o.v[c].re;
     q.y = (double)o.v[c].im;
-    f.data[f.cidx(rhs, par, c, s)] = q;
+    at(f.comp(rhs, par, c), s) = q;
   }
 }
 template <typename T>
@@ -224,7 +274,7 @@ __device__ __forceinline__ void store_spinor(const Field<float>& f, int rhs, int
     q.y = (float)o.v[2 * c].im;
     q.z = (float)o.v[2 * c + 1].re;
     q.w = (float)o.v[2 * c + 1].im;
-    f.data[f.cidx(rhs, par, c, s)] = q;
+    at(f.comp(rhs, par, c), s) = q;
   }
 }
 template <typename T>
@@ -233,7 +283,7 @@ __device__ __forceinline__ void store_spinor(const Field<_Float16>& f, int rhs, 
 #pragma unroll
   for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)o.v[c].re), fabsf((float)o.v[c].im)));
   const float inv = m > 0.f ? 1.0f / m : 0.f;
-  f.norm[f.nidx(rhs, par, s)] = m;
+  at(f.norm + (long)(rhs * 2 + par) * f.vh, s) = m;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     h8 q;
@@ -242,43 +292,159 @@ __device__ __forceinline__ void store_spinor(const Field<_Float16>& f, int rhs, 
       q[2 * k] = (_Float16)((float)o.v[4 * c + k].re * inv);
       q[2 * k + 1] = (_Float16)((float)o.v[4 * c + k].im * inv);
     }
-    f.data[f.cidx(rhs, par, c, s)] = q;
+    at(f.comp(rhs, par, c), s) = q;
   }
+}
+
+// ------------------------------------------------ buffer loads (scalar base)
+// A raw buffer resource over `bytes` bytes from base (no stride; the last
+// word is the gfx9-family default for untyped loads).  It lives in scalar
+// registers, so base must be uniform over the wavefront; every load names a
+// 32-bit lane offset and a 32-bit scalar offset, and a load past `bytes`
+// returns zero instead of touching memory.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename C>
+__device__ __forceinline__ C buf_load(rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(C) == 16)
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  else if constexpr (sizeof(C) == 8)
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// The spinor at site s of (rhs, par) through one buffer resource for the
+// whole (rhs, par) field: the components share the lane offset and differ by
+// a scalar one.  rhs and par must be uniform over the wavefront, and the
+// field of one (rhs, par) must span less than 4 GiB (the lattice limit).
+template <typename T>
+__device__ __forceinline__ void buf_load_spinor(const Field<double>& f, int rhs, int par, int s, Spinor<T>& o) {
+  const unsigned cb = (unsigned)f.vh * 16u;
+  const rsrc_t rs = buf_rsrc(f.comp(rhs, par, 0), 12u * cb);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const d2 q = buf_load<d2>(rs, (unsigned)s * 16u, c * cb);
+    o.v[c] = {(T)q.x, (T)q.y};
+  }
+}
+template <typename T>
+__device__ __forceinline__ void buf_load_spinor(const Field<float>& f, int rhs, int par, int s, Spinor<T>& o) {
+  const unsigned cb = (unsigned)f.vh * 16u;
+  const rsrc_t rs = buf_rsrc(f.comp(rhs, par, 0), 6u * cb);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const f4 q = buf_load<f4>(rs, (unsigned)s * 16u, c * cb);
+    o.v[2 * c] = {(T)q.x, (T)q.y};
+    o.v[2 * c + 1] = {(T)q.z, (T)q.w};
+  }
+}
+// FP16: the raw components; the site's norm is returned for the caller to apply.
+template <typename T>
+__device__ __forceinline__ float buf_load_spinor_raw(const Field<_Float16>& f, int rhs, int par, int s, Spinor<T>& o) {
+  const unsigned cb = (unsigned)f.vh * 16u;
+  const rsrc_t rs = buf_rsrc(f.comp(rhs, par, 0), 3u * cb);
+  const rsrc_t rn = buf_rsrc(f.norm + (long)(rhs * 2 + par) * f.vh, (unsigned)f.vh * 4u);
+  const float n = buf_load<float>(rn, (unsigned)s * 4u, 0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const h8 q = buf_load<h8>(rs, (unsigned)s * 16u, c * cb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o.v[4 * c + k] = {(T)(float)q[2 * k], (T)(float)q[2 * k + 1]};
+  }
+  return n;
+}
+
+// The third row of an SU(3) matrix from the first two: conj(row0 x row1),
+// each component a chain of four fused multiply-adds per real part.
+template <typename T>
+__device__ __forceinline__ void third_row(cpx<T> u[9]) {
+#define MFQ_CROSS(o, a, b, c, d) /* o = conj(a d - b c) */                                  \
+  {                                                                                        \
+    T re = u[a].re * u[d].re;                                                              \
+    re = fma(-u[a].im, u[d].im, re);                                                       \
+    re = fma(-u[b].re, u[c].re, re);                                                       \
+    re = fma(u[b].im, u[c].im, re);                                                        \
+    T im = -u[a].re * u[d].im;                                                             \
+    im = fma(-u[a].im, u[d].re, im);                                                       \
+    im = fma(u[b].re, u[c].im, im);                                                        \
+    im = fma(u[b].im, u[c].re, im);                                                        \
+    u[o] = {re, im};                                                                       \
+  }
+  MFQ_CROSS(6, 1, 2, 4, 5)
+  MFQ_CROSS(7, 2, 0, 5, 3)
+  MFQ_CROSS(8, 0, 1, 3, 4)
+#undef MFQ_CROSS
 }
 
 template <typename T>
 __device__ __forceinline__ void load_link(const Links<double>& l, int par, int mu, int s, cpx<T> u[9]) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    d2 q = l.data[l.idx(par, mu, k, s)];
+    d2 q = at(l.row(par, mu, k), s);
     u[k] = {(T)q.x, (T)q.y};
   }
 }
 template <typename T>
 __device__ __forceinline__ void load_link(const Links<float>& l, int par, int mu, int s, cpx<T> u[9]) {
-  {
-    const f4* c = (const f4*)l.data;
+  const f4* c = (const f4*)l.data;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      f4 q = c[l.cidx(par, mu, k, s)];
-      u[2 * k] = {(T)q.x, (T)q.y};
-      u[2 * k + 1] = {(T)q.z, (T)q.w};
-    }
-    third_row(u);
+  for (int k = 0; k < 3; ++k) {
+    f4 q = at(c + (long)((par * 4 + mu) * 3 + k) * l.vh, s);
+    u[2 * k] = {(T)q.x, (T)q.y};
+    u[2 * k + 1] = {(T)q.z, (T)q.w};
   }
+  third_row(u);
 }
 template <typename T>
 __device__ __forceinline__ void load_link(const Links<_Float16>& l, int par, int mu, int s, cpx<T> u[9]) {
-  {
-    const h4* c = (const h4*)l.data;
+  const h4* c = (const h4*)l.data;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      h4 q = c[l.cidx(par, mu, k, s)];
-      u[2 * k] = {(T)(float)q.x, (T)(float)q.y};
-      u[2 * k + 1] = {(T)(float)q.z, (T)(float)q.w};
-    }
-    third_row(u);
+  for (int k = 0; k < 3; ++k) {
+    h4 q = at(c + (long)((par * 4 + mu) * 3 + k) * l.vh, s);
+    u[2 * k] = {(T)(float)q.x, (T)(float)q.y};
+    u[2 * k + 1] = {(T)(float)q.z, (T)(float)q.w};
   }
+  third_row(u);
+}
+
+// Link U_mu(s) of parity par through one buffer resource per (par, mu)
+// (par uniform over the wavefront).
+template <typename T>
+__device__ __forceinline__ void buf_load_link(const Links<double>& l, int par, int mu, int s, cpx<T> u[9]) {
+  const unsigned cb = (unsigned)l.vh * 16u;
+  const rsrc_t rs = buf_rsrc(l.row(par, mu, 0), 9u * cb);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const d2 q = buf_load<d2>(rs, (unsigned)s * 16u, k * cb);
+    u[k] = {(T)q.x, (T)q.y};
+  }
+}
+template <typename T>
+__device__ __forceinline__ void buf_load_link(const Links<float>& l, int par, int mu, int s, cpx<T> u[9]) {
+  const unsigned cb = (unsigned)l.vh * 16u;
+  const rsrc_t rs = buf_rsrc((const f4*)l.data + (long)((par * 4 + mu) * 3) * l.vh, 3u * cb);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const f4 q = buf_load<f4>(rs, (unsigned)s * 16u, k * cb);
+    u[2 * k] = {(T)q.x, (T)q.y};
+    u[2 * k + 1] = {(T)q.z, (T)q.w};
+  }
+  third_row(u);
+}
+template <typename T>
+__device__ __forceinline__ void buf_load_link(const Links<_Float16>& l, int par, int mu, int s, cpx<T> u[9]) {
+  const unsigned cb = (unsigned)l.vh * 8u;
+  const rsrc_t rs = buf_rsrc((const h4*)l.data + (long)((par * 4 + mu) * 3) * l.vh, 3u * cb);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const h4 q = buf_load<h4>(rs, (unsigned)s * 8u, k * cb);
+    u[2 * k] = {(T)(float)q.x, (T)(float)q.y};
+    u[2 * k + 1] = {(T)(float)q.z, (T)(float)q.w};
+  }
+  third_row(u);
 }
 
 // -------------------------------------------------- Wilson hopping algebra
@@ -305,11 +471,9 @@ __device__ __forceinline__ void project(const Spinor<T>& p, T sg, int a, cpx<T>&
   }
 }
 
-// acc += [g ; sg e_mu^+ g]   (colour index a)
+// The lower two spins of acc += [g ; sg e_mu^+ g]   (colour index a)
 template <int MU, typename T>
-__device__ __forceinline__ void reconstruct(Spinor<T>& acc, T sg, int a, cpx<T> g0, cpx<T> g1) {
-  acc.v[a] = acc.v[a] + g0;
-  acc.v[3 + a] = acc.v[3 + a] + g1;
+__device__ __forceinline__ void reconstruct_lower(Spinor<T>& acc, T sg, int a, cpx<T> g0, cpx<T> g1) {
   if constexpr (MU == 0) {  // e^+ g = (-g0, -g1)
     acc.v[6 + a] = acc.v[6 + a] - sg * g0;
     acc.v[9 + a] = acc.v[9 + a] - sg * g1;
@@ -323,6 +487,14 @@ __device__ __forceinline__ void reconstruct(Spinor<T>& acc, T sg, int a, cpx<T> 
     acc.v[6 + a] = acc.v[6 + a] + sg * imul(g0);
     acc.v[9 + a] = acc.v[9 + a] - sg * imul(g1);
   }
+}
+
+// acc += [g ; sg e_mu^+ g]   (colour index a)
+template <int MU, typename T>
+__device__ __forceinline__ void reconstruct(Spinor<T>& acc, T sg, int a, cpx<T> g0, cpx<T> g1) {
+  acc.v[a] = acc.v[a] + g0;
+  acc.v[3 + a] = acc.v[3 + a] + g1;
+  reconstruct_lower<MU>(acc, sg, a, g0, g1);
 }
 
 // ---------------------------------------------------------- reductions

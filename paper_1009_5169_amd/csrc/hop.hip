@@ -31,12 +31,13 @@ __device__ __forceinline__ int tile_index(int remap) {
 template <typename S, typename SX>
 __device__ __forceinline__ int tile_site0(const HopArgs<S, SX>& a, int k, int sb) {
   if (!a.zb) return k * sb;
-  const int yt = k % a.tpp;
-  int rest = k / a.tpp;
-  const int zi = rest % a.zb;
-  rest /= a.zb;
-  const int t = rest % a.g.td;
-  const int z = (rest / a.g.td) * a.zb + zi;
+  int rest = fdiv(k, a.mtpp);
+  const int yt = k - rest * a.tpp;
+  const int zi = rest & (a.zb - 1);
+  rest >>= a.zbl;
+  const int q = fdiv(rest, a.mtd);
+  const int t = rest - q * a.g.td;
+  const int z = q * a.zb + zi;
   return yt * sb + a.g.lxh * a.g.ly * (z + a.g.lz * t);
 }
 
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(512) void hop_kernel(HopArgs<S, SX> a) {
     s0 = tile_site0(a, tile, blockDim.x);
   }
   const int s = s0 + threadIdx.x;
-  const int r = blockIdx.y * blockDim.y + threadIdx.y;
+  const int r = wave_uniform(blockIdx.y * blockDim.y + threadIdx.y);  // blockDim.x is a multiple of 64
   double av = 0.0;
   if constexpr (EPI == EPI_CGUPD) av = alpha_fetch(a, r, threadIdx.x < 64);
   bool active = s < a.g.vh && r < a.n_rhs;
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(512) void hop_sweep_kernel(HopArgs<S, SX> a, int tc
   const int tile = tile_index(a.xcd);
   const int chunk = tile / nsb;
   const int sigma = (tile - chunk * nsb) * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y * blockDim.y + threadIdx.y;
+  const int r = wave_uniform(blockIdx.y * blockDim.y + threadIdx.y);  // blockDim.x is a multiple of 64
   const Geom& g = a.g;
   double alpha = 0.0;
   if constexpr (EPI == EPI_CGUPD)
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(512) void hop_sweep_kernel(HopArgs<S, SX> a, int tc
     const int t1 = t0 + tc < g.td ? t0 + tc : g.td;
     for (c.t = t0; c.t < t1; ++c.t) {
       const int par = (c.x + c.y + c.z + c.t + g.t0) & 1;
-      red += hop_site<EPI>(a, par, half_index(g, c.x, c.y, c.z, c.t), c, r, alpha);
+      red += hop_site<EPI, false>(a, par, half_index(g, c.x, c.y, c.z, c.t), c, r, alpha);  // par varies per lane
     }
   }
   if (a.part) block_partial(red, a.part, a.n_rhs, blockIdx.y * blockDim.y, blockIdx.x, gridDim.x);
@@ -201,7 +202,8 @@ __global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
   } else {
     s = tile_site0(a, tile, 64) + threadIdx.x;
   }
-  const int row = threadIdx.y / DS, w = threadIdx.y - row * DS;
+  const int ty = wave_uniform(threadIdx.y);  // blockDim.x is 64
+  const int row = ty / DS, w = ty - row * DS;
   const int r = blockIdx.y * (blockDim.y / DS) + row;
   double av = 0.0;
   if constexpr (EPI == EPI_CGUPD) av = alpha_fetch(a, r, w == 0);
@@ -232,21 +234,22 @@ __global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
   double alpha = 0.0;
   if constexpr (EPI == EPI_CGUPD) alpha = alpha_finish(a, r, row, w == 0, av);
   else __syncthreads();
-  if (w != 0) return;
-  double red = 0.0;
-  if (active) {
+  if (w == 0) {
+    double red = 0.0;
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < DS - 1; ++q)
+      for (int q = 0; q < DS - 1; ++q)
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        acc.v[k].re += lds[row][q][2 * k][threadIdx.x];
-        acc.v[k].im += lds[row][q][2 * k + 1][threadIdx.x];
-      }
-    red = hop_epilogue<EPI>(a, par, s, r, alpha, acc);
-  }
-  if (a.part) {
-    red = wave_sum(red);
-    if (threadIdx.x == 0 && r < a.n_rhs) a.part[(long)r * gridDim.x + blockIdx.x] = red;
+        for (int k = 0; k < 12; ++k) {
+          acc.v[k].re += lds[row][q][2 * k][threadIdx.x];
+          acc.v[k].im += lds[row][q][2 * k + 1][threadIdx.x];
+        }
+      red = hop_epilogue<EPI>(a, par, s, r, alpha, acc);
+    }
+    if (a.part) {
+      red = wave_sum(red);
+      if (threadIdx.x == 0 && r < a.n_rhs) a.part[(long)r * gridDim.x + blockIdx.x] = red;
+    }
   }
 }
 
@@ -260,66 +263,33 @@ __global__ __launch_bounds__(512) void hop_split_kernel(HopArgs<S, SX> a) {
 template <int MU, int R, typename S, typename SX, typename T>
 __device__ __forceinline__ void hop_dir_rt(const HopArgs<S, SX>& a, int par, const Coords& c, int s, const int (&rr)[R],
                                            T sgf, T sgb, Spinor<T> (&acc)[R]) {
-  const Geom& g = a.g;
   const int po = 1 - par;
-  int xf = c.x, yf = c.y, zf = c.z, tf = c.t;
-  int xb = c.x, yb = c.y, zb = c.z, tb = c.t;
-  T wf = (T)1, wb = (T)1;
-  if constexpr (MU == 0) {
-    const T wrap = g.bc == BC_SF ? (T)0 : (g.bc == BC_ANTIPERIODIC ? (T)-1 : (T)1);
-    tf = c.t + 1;
-    if (tf == g.td) {
-      tf = 0;
-      wf = wrap;
-    }
-    tb = c.t - 1;
-    if (tb < 0) {
-      tb = g.td - 1;
-      wb = wrap;
-    }
-  } else if constexpr (MU == 1) {
-    xf = (c.x + 1 == g.lx) ? 0 : c.x + 1;
-    xb = (c.x == 0) ? g.lx - 1 : c.x - 1;
-  } else if constexpr (MU == 2) {
-    yf = (c.y + 1 == g.ly) ? 0 : c.y + 1;
-    yb = (c.y == 0) ? g.ly - 1 : c.y - 1;
-  } else {
-    zf = (c.z + 1 == g.lz) ? 0 : c.z + 1;
-    zb = (c.z == 0) ? g.lz - 1 : c.z - 1;
-  }
-  const int sf = half_index(g, xf, yf, zf, tf);
-  const int sbk = half_index(g, xb, yb, zb, tb);
+  int sf, sbk;
+  neighbours<MU>(a.g, c, s, sf, sbk);
+  T wf, wb;
+  time_factors<MU>(a.g, c, wf, wb);
+  // 64-bit per-lane addresses here: a scalar buffer resource per RHS of the
+  // group would exhaust the scalar registers.
+  const PlainSrc<S, T> src{a.in};
   cpx<T> u[9];
   load_link(a.links, par, MU, s, u);
 #pragma unroll
   for (int q = 0; q < R; ++q) {  // forward: (1 + sgf g_mu) U_mu(n) psi(n + mu)
     Spinor<T> nb;
-    load_spinor(a.in, rr[q], po, sf, nb);
-    cpx<T> h0[3], h1[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) project<MU>(nb, sgf, k, h0[k], h1[k]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const cpx<T> g0 = cmul(u[3 * i], h0[0]) + cmul(u[3 * i + 1], h0[1]) + cmul(u[3 * i + 2], h0[2]);
-      const cpx<T> g1 = cmul(u[3 * i], h1[0]) + cmul(u[3 * i + 1], h1[1]) + cmul(u[3 * i + 2], h1[2]);
-      reconstruct<MU>(acc[q], sgf, i, wf * g0, wf * g1);
-    }
+    const T ns = src.load(rr[q], po, sf, nb);
+    hop_half<MU, false, !std::is_same<S, _Float16>::value>(nb, u, sgf, wf * ns, acc[q]);
   }
+  // keep the compiler from hoisting the next loads over this half: R
+  // spinors in flight per half already cover the latency, more do not fit
+  __builtin_amdgcn_sched_barrier(0);
   load_link(a.links, po, MU, sbk, u);
 #pragma unroll
   for (int q = 0; q < R; ++q) {  // backward: U_mu(n - mu)^+ psi(n - mu)
     Spinor<T> nb;
-    load_spinor(a.in, rr[q], po, sbk, nb);
-    cpx<T> h0[3], h1[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) project<MU>(nb, sgb, k, h0[k], h1[k]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const cpx<T> g0 = cjmul(u[i], h0[0]) + cjmul(u[3 + i], h0[1]) + cjmul(u[6 + i], h0[2]);
-      const cpx<T> g1 = cjmul(u[i], h1[0]) + cjmul(u[3 + i], h1[1]) + cjmul(u[6 + i], h1[2]);
-      reconstruct<MU>(acc[q], sgb, i, wb * g0, wb * g1);
-    }
+    const T ns = src.load(rr[q], po, sbk, nb);
+    hop_half<MU, true, !std::is_same<S, _Float16>::value>(nb, u, sgb, wb * ns, acc[q]);
   }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int EPI, int R, typename S, typename SX>
@@ -466,7 +436,10 @@ hipError_t launch_hop(int epi, const HopArgs<S, SX>& a, Shape sh, hipStream_t st
     const int plane = a.g.lxh * a.g.ly;  // half sites per (z, t) plane
     if ((sh.xcd & 2) && (sh.tc == 0 || sh.ds > 1) && plane % sbe == 0) {
       b.zb = a.g.lz % 4 == 0 ? 4 : (a.g.lz % 2 == 0 ? 2 : 1);
+      b.zbl = b.zb == 4 ? 2 : (b.zb == 2 ? 1 : 0);
       b.tpp = plane / sbe;
+      b.mtpp = fdiv_magic(b.tpp);
+      b.mtd = fdiv_magic(a.g.td);
     }
   }
   if (sh.ds == 2 || sh.ds == 4) {

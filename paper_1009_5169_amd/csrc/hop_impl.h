@@ -6,6 +6,8 @@
 // and its adjoint (projector signs swapped); D = 1 - kappa H.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mfq {
@@ -52,12 +54,48 @@ __device__ __forceinline__ void block_partial(double v, double* part, int n_rhs,
   __syncthreads();
 }
 
-// Where the hopping term reads its input spinors.
+// Where the hopping term reads its input spinors.  load() returns the factor
+// the spinor still has to be multiplied by: 1, or for FP16 storage the
+// site's norm, which the hopping term folds into its accumulation.
 template <typename S, typename T>
 struct PlainSrc {
   Field<S> f;
-  __device__ __forceinline__ void load(int r, int par, int s, Spinor<T>& o) const { load_spinor(f, r, par, s, o); }
+  __device__ __forceinline__ T load(int r, int par, int s, Spinor<T>& o) const {
+    load_spinor(f, r, par, s, o);
+    return (T)1;
+  }
 };
+template <typename T>
+struct PlainSrc<_Float16, T> {
+  Field<_Float16> f;
+  __device__ __forceinline__ T load(int r, int par, int s, Spinor<T>& o) const {
+    const float n = load_norm(f, r, par, s);
+    load_spinor_raw(f, r, par, s, o);
+    return (T)n;
+  }
+};
+
+// The same through buffer resources: (r, par) uniform over the wavefront.
+template <typename S, typename T>
+struct BufSrc {
+  Field<S> f;
+  __device__ __forceinline__ T load(int r, int par, int s, Spinor<T>& o) const {
+    buf_load_spinor(f, r, par, s, o);
+    return (T)1;
+  }
+};
+template <typename T>
+struct BufSrc<_Float16, T> {
+  Field<_Float16> f;
+  __device__ __forceinline__ T load(int r, int par, int s, Spinor<T>& o) const {
+    return (T)buf_load_spinor_raw(f, r, par, s, o);
+  }
+};
+
+// A wave-uniform value (threadIdx.y of a workgroup whose x extent is a
+// multiple of 64, anything derived from blockIdx) read into a scalar
+// register, so that the addresses built from it stay scalar.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Where the hopping term reads its links: the global arrays, or an LDS tile
 // holding, for each site of the workgroup's tile, its 4 forward links U_mu(n)
@@ -70,6 +108,16 @@ struct GlobalLinks {
   __device__ __forceinline__ void fwd(int par, int s, cpx<T> u[9]) const { load_link(L, par, MU, s, u); }
   template <int MU, typename T>
   __device__ __forceinline__ void bwd(int po, int sbk, cpx<T> u[9]) const { load_link(L, po, MU, sbk, u); }
+};
+
+// The links through buffer resources (par uniform over the wavefront).
+template <typename S>
+struct BufLinks {
+  Links<S> L;
+  template <int MU, typename T>
+  __device__ __forceinline__ void fwd(int par, int s, cpx<T> u[9]) const { buf_load_link(L, par, MU, s, u); }
+  template <int MU, typename T>
+  __device__ __forceinline__ void bwd(int po, int sbk, cpx<T> u[9]) const { buf_load_link(L, po, MU, sbk, u); }
 };
 
 template <typename S>
@@ -115,73 +163,141 @@ __device__ __forceinline__ int back_neighbour(const Geom& g, const Coords& c) {
   return half_index(g, x, y, z, t);
 }
 
+// Half-lattice indices of the forward and backward neighbours of site s in
+// direction MU: a step by the direction's stride, or the jump of a periodic
+// wrap (the time boundary's factor is applied by the caller), from the
+// site's coordinates without a multiply.  In x a step moves the half index
+// only from an odd x forwards and from an even x backwards.
+template <int MU>
+__device__ __forceinline__ void neighbours(const Geom& g, const Coords& c, int s, int& sf, int& sb) {
+  if constexpr (MU == 0) {
+    sf = s + (c.t + 1 == g.td ? -g.wt : g.st);
+    sb = s - (c.t == 0 ? -g.wt : g.st);
+  } else if constexpr (MU == 1) {
+    const bool odd = c.x & 1;
+    sf = s + (odd ? (c.x + 1 == g.lx ? 1 - g.lxh : 1) : 0);
+    sb = s - (odd ? 0 : (c.x == 0 ? 1 - g.lxh : 1));
+  } else if constexpr (MU == 2) {
+    sf = s + (c.y + 1 == g.ly ? -g.wy : g.sy);
+    sb = s - (c.y == 0 ? -g.wy : g.sy);
+  } else {
+    sf = s + (c.z + 1 == g.lz ? -g.wz : g.sz);
+    sb = s - (c.z == 0 ? -g.wz : g.sz);
+  }
+}
+
+// o += a b and o += conj(a) b as chains of fused multiply-adds.
+template <typename T>
+__device__ __forceinline__ void cmac(cpx<T>& o, cpx<T> a, cpx<T> b) {
+  o.re = fma(a.re, b.re, o.re);
+  o.re = fma(-a.im, b.im, o.re);
+  o.im = fma(a.re, b.im, o.im);
+  o.im = fma(a.im, b.re, o.im);
+}
+template <typename T>
+__device__ __forceinline__ void cjmac(cpx<T>& o, cpx<T> a, cpx<T> b) {
+  o.re = fma(a.re, b.re, o.re);
+  o.re = fma(a.im, b.im, o.re);
+  o.im = fma(a.re, b.im, o.im);
+  o.im = fma(-a.im, b.re, o.im);
+}
+
+// acc += w [g ; sg e_mu^+ g] for colour a, with sgw = sg w.
+template <int MU, typename T>
+__device__ __forceinline__ void reconstruct_w(Spinor<T>& acc, T w, T sgw, int a, cpx<T> g0, cpx<T> g1) {
+  acc.v[a].re = fma(w, g0.re, acc.v[a].re);
+  acc.v[a].im = fma(w, g0.im, acc.v[a].im);
+  acc.v[3 + a].re = fma(w, g1.re, acc.v[3 + a].re);
+  acc.v[3 + a].im = fma(w, g1.im, acc.v[3 + a].im);
+  reconstruct_lower<MU>(acc, sgw, a, g0, g1);
+}
+
+// One half of direction MU: acc += w (1 + sg g_mu) V n with V = U (forward
+// hop) or U^+ (backward hop, DAG): the projection to two spins, the colour
+// multiply of both, and the accumulation into all four spins.  FUSED: the
+// colour multiply as chains of fused multiply-adds and w folded into the
+// accumulation.  For FP16 storage the compiler then keeps the half-precision
+// operands packed for mixed-precision FMAs and runs out of registers, so
+// FP16 takes the plain sums (FUSED = false).
+template <int MU, bool DAG, bool FUSED, typename T>
+__device__ __forceinline__ void hop_half(const Spinor<T>& n, const cpx<T> u[9], T sg, T w, Spinor<T>& acc) {
+  cpx<T> h0[3], h1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) project<MU>(n, sg, k, h0[k], h1[k]);
+  if constexpr (!FUSED) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cpx<T> g0, g1;
+      if constexpr (!DAG) {
+        g0 = cmul(u[3 * i], h0[0]) + cmul(u[3 * i + 1], h0[1]) + cmul(u[3 * i + 2], h0[2]);
+        g1 = cmul(u[3 * i], h1[0]) + cmul(u[3 * i + 1], h1[1]) + cmul(u[3 * i + 2], h1[2]);
+      } else {
+        g0 = cjmul(u[i], h0[0]) + cjmul(u[3 + i], h0[1]) + cjmul(u[6 + i], h0[2]);
+        g1 = cjmul(u[i], h1[0]) + cjmul(u[3 + i], h1[1]) + cjmul(u[6 + i], h1[2]);
+      }
+      reconstruct<MU>(acc, sg, i, w * g0, w * g1);
+    }
+    return;
+  }
+  const T sgw = sg * w;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    cpx<T> g0, g1;
+    if constexpr (!DAG) {
+      g0 = cmul(u[3 * i], h0[0]);
+      g1 = cmul(u[3 * i], h1[0]);
+      cmac(g0, u[3 * i + 1], h0[1]);
+      cmac(g1, u[3 * i + 1], h1[1]);
+      cmac(g0, u[3 * i + 2], h0[2]);
+      cmac(g1, u[3 * i + 2], h1[2]);
+    } else {  // (U^+)_{ik} = conj(U_{ki})
+      g0 = cjmul(u[i], h0[0]);
+      g1 = cjmul(u[i], h1[0]);
+      cjmac(g0, u[3 + i], h0[1]);
+      cjmac(g1, u[3 + i], h1[1]);
+      cjmac(g0, u[6 + i], h0[2]);
+      cjmac(g1, u[6 + i], h1[2]);
+    }
+    reconstruct_w<MU>(acc, w, sgw, i, g0, g1);
+  }
+}
+
+// The factors of the forward and backward time hops: 1 inside, and across
+// the time boundary 0 (Schroedinger functional: the neighbour is a boundary
+// slice, outside the dynamical field), -1 (antiperiodic) or 1 (periodic).
+template <int MU, typename T>
+__device__ __forceinline__ void time_factors(const Geom& g, const Coords& c, T& wf, T& wb) {
+  wf = (T)1;
+  wb = (T)1;
+  if constexpr (MU == 0) {
+    const T wrap = g.bc == BC_SF ? (T)0 : (g.bc == BC_ANTIPERIODIC ? (T)-1 : (T)1);
+    if (c.t + 1 == g.td) wf = wrap;
+    if (c.t == 0) wb = wrap;
+  }
+}
+
 // One direction mu of the hopping term: forward hop from n+mu through U_mu(n),
 // backward hop from n-mu through U_mu(n-mu)^+.  sgf / sgb are the projector
-// signs (-1 / +1 for H, +1 / -1 for H^+).  The time boundary is folded into a
-// factor (0 across a Schroedinger-functional boundary, -1 across an
-// antiperiodic wrap) on a neighbour index that always stays inside the
-// lattice, so the loads of every direction are unconditional and can be
-// issued together.
+// signs (-1 / +1 for H, +1 / -1 for H^+).  The time boundary is a factor on
+// a neighbour index that always stays inside the lattice, so the loads of
+// every direction are unconditional and can be issued together.
 template <int MU, typename S, typename SX, typename T, typename Src, typename LS>
 __device__ __forceinline__ void hop_dir(const HopArgs<S, SX>& a, const Src& src, const LS& lk, int par,
                                         const Coords& c, int s, int r, T sgf, T sgb, Spinor<T>& acc) {
-  const Geom& g = a.g;
   const int po = 1 - par;
-  int xf = c.x, yf = c.y, zf = c.z, tf = c.t;
-  int xb = c.x, yb = c.y, zb = c.z, tb = c.t;
-  T wf = (T)1, wb = (T)1;
-  if constexpr (MU == 0) {
-    const T wrap = g.bc == BC_SF ? (T)0 : (g.bc == BC_ANTIPERIODIC ? (T)-1 : (T)1);
-    tf = c.t + 1;
-    if (tf == g.td) {
-      tf = 0;
-      wf = wrap;
-    }
-    tb = c.t - 1;
-    if (tb < 0) {
-      tb = g.td - 1;
-      wb = wrap;
-    }
-  } else if constexpr (MU == 1) {
-    xf = (c.x + 1 == g.lx) ? 0 : c.x + 1;
-    xb = (c.x == 0) ? g.lx - 1 : c.x - 1;
-  } else if constexpr (MU == 2) {
-    yf = (c.y + 1 == g.ly) ? 0 : c.y + 1;
-    yb = (c.y == 0) ? g.ly - 1 : c.y - 1;
-  } else {
-    zf = (c.z + 1 == g.lz) ? 0 : c.z + 1;
-    zb = (c.z == 0) ? g.lz - 1 : c.z - 1;
-  }
-  const int sf = half_index(g, xf, yf, zf, tf);
-  const int sbk = half_index(g, xb, yb, zb, tb);
+  int sf, sbk;
+  neighbours<MU>(a.g, c, s, sf, sbk);
+  T wf, wb;
+  time_factors<MU>(a.g, c, wf, wb);
   Spinor<T> nf, nb;
   cpx<T> uf[9], ub[9];
-  src.load(r, po, sf, nf);
+  const T nsf = src.load(r, po, sf, nf);
   lk.template fwd<MU>(par, s, uf);
-  src.load(r, po, sbk, nb);
+  const T nsb = src.load(r, po, sbk, nb);
   lk.template bwd<MU>(po, sbk, ub);
-  {  // forward
-    cpx<T> h0[3], h1[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) project<MU>(nf, sgf, k, h0[k], h1[k]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      cpx<T> g0 = cmul(uf[3 * i], h0[0]) + cmul(uf[3 * i + 1], h0[1]) + cmul(uf[3 * i + 2], h0[2]);
-      cpx<T> g1 = cmul(uf[3 * i], h1[0]) + cmul(uf[3 * i + 1], h1[1]) + cmul(uf[3 * i + 2], h1[2]);
-      reconstruct<MU>(acc, sgf, i, wf * g0, wf * g1);
-    }
-  }
-  {  // backward: (U^+)_{ik} = conj(U_{ki})
-    cpx<T> h0[3], h1[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) project<MU>(nb, sgb, k, h0[k], h1[k]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      cpx<T> g0 = cjmul(ub[i], h0[0]) + cjmul(ub[3 + i], h0[1]) + cjmul(ub[6 + i], h0[2]);
-      cpx<T> g1 = cjmul(ub[i], h1[0]) + cjmul(ub[3 + i], h1[1]) + cjmul(ub[6 + i], h1[2]);
-      reconstruct<MU>(acc, sgb, i, wb * g0, wb * g1);
-    }
-  }
+  constexpr bool F = !std::is_same<S, _Float16>::value;
+  hop_half<MU, false, F>(nf, uf, sgf, wf * nsf, acc);
+  hop_half<MU, true, F>(nb, ub, sgb, wb * nsb, acc);
 }
 
 // The per-RHS CG scalar recursion, applied once the reduction `sum` of the
@@ -247,22 +363,29 @@ __device__ __forceinline__ void cg_scalar_update(int fin, CgScalars& s, double s
 
 
 // Directions [MU0, MU1) of the hopping term at output site s, accumulated into acc.
-template <int MU0, int MU1, typename S, typename SX, typename T, typename LS>
+// UNI: r and par are uniform over the wavefront, so the spinors and links
+// are read through scalar buffer resources; otherwise through 64-bit
+// per-lane addresses.
+template <int MU0, int MU1, bool UNI = true, typename S, typename SX, typename T, typename LS>
 __device__ __forceinline__ void hop_dirs_with(const HopArgs<S, SX>& a, const LS& lk, int par, int s,
                                               const Coords& c, int r, Spinor<T>& acc) {
   const T sgf = a.dagger ? (T)1 : (T)-1;
   const T sgb = -sgf;
-  PlainSrc<S, T> src{a.in};
+  using Src = typename std::conditional<UNI, BufSrc<S, T>, PlainSrc<S, T>>::type;
+  const Src src{a.in};
   if constexpr (MU0 <= 0 && 0 < MU1) hop_dir<0>(a, src, lk, par, c, s, r, sgf, sgb, acc);
   if constexpr (MU0 <= 1 && 1 < MU1) hop_dir<1>(a, src, lk, par, c, s, r, sgf, sgb, acc);
   if constexpr (MU0 <= 2 && 2 < MU1) hop_dir<2>(a, src, lk, par, c, s, r, sgf, sgb, acc);
   if constexpr (MU0 <= 3 && 3 < MU1) hop_dir<3>(a, src, lk, par, c, s, r, sgf, sgb, acc);
 }
 
-template <int MU0, int MU1, typename S, typename SX, typename T>
+template <int MU0, int MU1, bool UNI = true, typename S, typename SX, typename T>
 __device__ __forceinline__ void hop_dirs(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
                                          Spinor<T>& acc) {
-  hop_dirs_with<MU0, MU1>(a, GlobalLinks<S>{a.links}, par, s, c, r, acc);
+  if constexpr (UNI)
+    hop_dirs_with<MU0, MU1, true>(a, BufLinks<S>{a.links}, par, s, c, r, acc);
+  else
+    hop_dirs_with<MU0, MU1, false>(a, GlobalLinks<S>{a.links}, par, s, c, r, acc);
 }
 
 // The epilogue applied to the complete hopping term acc at output site s;
@@ -320,13 +443,13 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<S, SX>& a, int par,
 
 // The hopping term at output site s of parity par for RHS r, followed by the
 // epilogue (alpha is the CG step length, used by EPI_CGUPD).
-template <int EPI, typename S, typename SX>
+template <int EPI, bool UNI = true, typename S, typename SX>
 __device__ __forceinline__ double hop_site(const HopArgs<S, SX>& a, int par, int s, const Coords& c, int r,
                                            double al) {
   using T = typename Compute<S>::T;
   Spinor<T> acc;
   zero(acc);
-  hop_dirs<0, 4>(a, par, s, c, r, acc);
+  hop_dirs<0, 4, UNI>(a, par, s, c, r, acc);
   return hop_epilogue<EPI>(a, par, s, r, al, acc);
 }
 

@@ -113,6 +113,8 @@ struct HopArgs {
   // and a link's t and z neighbours are read a few dozen tiles apart, inside
   // one XCD's L2, instead of a whole time slice apart.  tpp = tiles per plane.
   int zb, tpp;
+  int zbl;             // log2(zb) (zb is 1, 2 or 4)
+  unsigned mtpp, mtd;  // division magic (fdiv) of tpp and of the dynamical time extent
   double coef;         // coefficient of the hopping term
 };
 
