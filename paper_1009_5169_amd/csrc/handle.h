@@ -42,6 +42,7 @@ struct PtcState {
   OwnedField<float> hid, y, gy, gh;
   OwnedField<double> pr, pe;  // packed training pairs (residuals, errors)
   DevBuf ops, chi;  // matrix-core weight operands; layer-2 mixings before transport
+  DevBuf ops_train, ops_adj, wadj;  // training: hi/lo operands of the master and the adjoint weights
   int adam_t = 0;
   int w_version = 0, ops_version = -1;  // ops are rebuilt when the inference weights change
   bool have_weights = false;

@@ -74,8 +74,12 @@ def test_ptc_forward_matches_oracle(case):
     lat.close()
 
 
-def test_ptc_loss_and_gradient_match_oracle():
-    dims, bc = (4, 4, 2, 6), "sf"
+@pytest.mark.parametrize("case", [((4, 4, 2, 6), "sf"), ((4, 2, 2, 6), "sf"), ((2, 4, 2, 4), "antiperiodic")],
+                         ids=["sf-full-tiles", "sf-ragged-tile", "antiperiodic"])
+def test_ptc_loss_and_gradient_match_oracle(case):
+    """The gradients come from the matrix-core kernels (16-site tiles: the
+    second case has 20 sites per parity, a ragged last tile)."""
+    dims, bc = case
     u = synth.random_links(dims, bc, 0.5, 33)
     lat = mfq.Lattice(dims, bc, 0.12, to_dev(u))
     w1, w2 = ptc.init_weights(8, scale=0.3)
