@@ -439,8 +439,9 @@ def bench_fp16(synth, mfq, torch, dev, np, keep):
 def bench_learned(synth, mfq, torch, dev, np, keep):
     """16^3x16 SF, eps = 0.5, kappa = 0.1375, 5 evaluation RHS: train the PTC
     network on pairs from plain CG on b = A xi with known Gaussian solutions xi
-    (seeds 6000+), then FGMRES(16) with it, FGMRES(16) without it and plain
-    FP64 CG, all to 1e-10."""
+    (seeds 6000+), then FGMRES(16) with it and without it (the cycle in FP64,
+    and in FP32 with FP64 restarts), plain FP64 CG and CG with FP32 inner
+    solves, all to 1e-10."""
     p = synth.CONFIG_4
     print(f"[bench] row learned {p.name}", file=sys.stderr, flush=True)
     lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
@@ -460,15 +461,18 @@ def bench_learned(synth, mfq, torch, dev, np, keep):
            "pairs_s": round(t_pairs, 3), "train_s": round(t_train, 3),
            "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
     xs = {}
-    for name, kw in (("cg_fp64", dict(prec="fp64")), ("fgmres_identity", dict(prec="fp64", precond="identity")),
-                     ("fgmres_ptc", dict(prec="fp64", precond="ptc"))):
+    for name, kw in (("cg_fp64", dict(prec="fp64")), ("cg_fp32", dict(prec="fp32")),
+                     ("fgmres_identity", dict(prec="fp64", precond="identity")),
+                     ("fgmres_ptc", dict(prec="fp64", precond="ptc")),
+                     ("fgmres_identity_fp32", dict(prec="fp32", precond="identity")),
+                     ("fgmres_ptc_fp32", dict(prec="fp32", precond="ptc"))):
         pr = mfq.make_params(tol=1e-10, max_iter=50000, **kw)
         ms, (x, st, rc) = _timed(lambda: lat.solve(b, params=pr), reps=2)
         xs[name] = x.cpu().numpy()
         res[name] = {"ms": round(ms, 3), "rc": rc, "iters": [s["iters"] for s in st],
                      "true_rel_resid_max": max(s["true_rel_resid"] for s in st)}
     ref = xs["cg_fp64"]
-    for name in ("fgmres_identity", "fgmres_ptc"):
+    for name in ("cg_fp32", "fgmres_identity", "fgmres_ptc", "fgmres_identity_fp32", "fgmres_ptc_fp32"):
         res[name]["rel_err_vs_cg"] = float(np.linalg.norm(xs[name] - ref) / np.linalg.norm(ref))
     keep["learned_16x16x16x16"] = (p, {k: v[:1] for k, v in xs.items()})
     res["ptc_iteration_gain_vs_fgmres"] = round(sum(res["fgmres_identity"]["iters"]) /
@@ -476,6 +480,9 @@ def bench_learned(synth, mfq, torch, dev, np, keep):
     # time ratios against plain FP64 CG (> 1: slower than CG)
     res["ptc_ms_over_cg_ms"] = round(res["fgmres_ptc"]["ms"] / res["cg_fp64"]["ms"], 3)
     res["identity_ms_over_cg_ms"] = round(res["fgmres_identity"]["ms"] / res["cg_fp64"]["ms"], 3)
+    # the FGMRES cycle in FP32 (basis, operator, network input and output; FP64 restarts)
+    res["ptc_fp32_ms_over_cg_ms"] = round(res["fgmres_ptc_fp32"]["ms"] / res["cg_fp64"]["ms"], 3)
+    res["ptc_fp32_ms_over_cg_fp32_ms"] = round(res["fgmres_ptc_fp32"]["ms"] / res["cg_fp32"]["ms"], 3)
     lat.close()
     return res
 

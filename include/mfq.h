@@ -113,7 +113,10 @@ typedef enum {
 typedef enum { MFQ_ROUTE_FULL = 0, MFQ_ROUTE_SCHUR = 1 } mfq_route;
 
 /* Solver selection: NONE is CG on D^+D; PTC is restarted flexible GMRES
- * (restart = mfq_solve_params.restart, FP64 Arnoldi) right-preconditioned by
+ * (restart = mfq_solve_params.restart; prec FP64: the cycle in FP64, else
+ * the basis, the operator inside the cycle and the network's input and
+ * output in FP32, with FP64 dot-product sums, solution and true-residual
+ * restarts) right-preconditioned by
  * the learned parallel-transport network, with CG as the fallback when a
  * cycle stagnates or breaks down (status MFQ_FELL_BACK); IDENTITY is the same
  * GMRES without preconditioner (the reference the network is measured

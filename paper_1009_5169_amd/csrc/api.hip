@@ -864,6 +864,14 @@ int fp64_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out) {
   return tuned_shape<double, double>(h, n, 8, links_d(h), w.pd.view(g), w.td.view(g), st, out);
 }
 
+int fp32_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out) {
+  Workspace& w = h->ws;
+  const Geom& g = h->g;
+  HIPCHK(w.ps.alloc(g, n));
+  HIPCHK(w.ts.alloc(g, n));
+  return tuned_shape<float, float>(h, n, 4, links_f(h), w.ps.view(g), w.ts.view(g), st, out);
+}
+
 int ensure_fp64_fields(mfq_handle* h, int n) {
   Workspace& w = h->ws;
   HIPCHK(w.b64.alloc(h->g, n));

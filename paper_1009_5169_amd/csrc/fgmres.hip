@@ -62,8 +62,8 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* part_a, d
 // and meet in one workgroup reduction.  The second pass runs only for the RHS
 // whose first pass asked for it (the whole workgroup belongs to one RHS, so it
 // returns together).
-template <int NV>
-__global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> V, size_t vstride, Field<double> w,
+template <int NV, typename S>
+__global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<S> V, size_t vstride, Field<S> w,
                                                           int n_rhs, double* part, int first, const GmState* st) {
   GM_LANE
   if (!first && !st[r].reorth) return;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<double> 
     for (int k = 0; k < 12; ++k) acc[2 * NV] += norm2(ww.v[k]);
 #pragma unroll
     for (int l = 0; l < NV; ++l) {
-      Field<double> vl = V;
+      Field<S> vl = V;
       vl.data += l * vstride;
       Spinor<double> vv;
       load_spinor(vl, r, par, s, vv);
@@ -157,8 +157,8 @@ __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int 
 // in the span of the basis; each cycle restarts from the FP64 true residual,
 // so lost orthogonality could only cost iterations.)  No other workgroup of
 // this launch reads the flag.
-template <int NV>
-__global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double> V, size_t vstride, Field<double> w,
+template <int NV, typename S>
+__global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<S> V, size_t vstride, Field<S> w,
                                                            int n_rhs, GmState* st, int first) {
   GM_LANE
   if (!first && !st[r].reorth) return;
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double>
 #pragma unroll
   for (int l = 0; l < NV; ++l) {
     const cpx<double> c = {st[r].cr[l], st[r].ci[l]};
-    Field<double> vl = V;
+    Field<S> vl = V;
     vl.data += l * vstride;
     Spinor<double> vv;
     load_spinor(vl, r, par, s, vv);
@@ -189,12 +189,13 @@ __global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<double>
   X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 static_assert(GM_MAXM == 32, "one multidot / multiaxpy instance per basis size 1..GM_MAXM");
 
-hipError_t launch_multidot(int nv, dim3 grid, dim3 blk, hipStream_t st, const Geom& g, Field<double> V,
-                           size_t vstride, Field<double> w, int n, double* part, int first, const GmState* S) {
+template <typename SV>
+hipError_t launch_multidot(int nv, dim3 grid, dim3 blk, hipStream_t st, const Geom& g, Field<SV> V,
+                           size_t vstride, Field<SV> w, int n, double* part, int first, const GmState* S) {
   switch (nv) {
 #define GM_DOT(N)                                                                                                \
   case N:                                                                                                        \
-    hipLaunchKernelGGL((gm_multidot_kernel<N>), grid, blk, 0, st, g, V, vstride, w, n, part, first, S);          \
+    hipLaunchKernelGGL((gm_multidot_kernel<N, SV>), grid, blk, 0, st, g, V, vstride, w, n, part, first, S);      \
     break;
     GM_NV_CASES(GM_DOT)
 #undef GM_DOT
@@ -203,12 +204,13 @@ hipError_t launch_multidot(int nv, dim3 grid, dim3 blk, hipStream_t st, const Ge
   return hipGetLastError();
 }
 
-hipError_t launch_multiaxpy(int nv, dim3 grid, dim3 blk, hipStream_t st, const Geom& g, Field<double> V,
-                            size_t vstride, Field<double> w, int n, GmState* S, int first) {
+template <typename SV>
+hipError_t launch_multiaxpy(int nv, dim3 grid, dim3 blk, hipStream_t st, const Geom& g, Field<SV> V,
+                            size_t vstride, Field<SV> w, int n, GmState* S, int first) {
   switch (nv) {
 #define GM_AXPY(N)                                                                                               \
   case N:                                                                                                        \
-    hipLaunchKernelGGL((gm_multiaxpy_kernel<N>), grid, blk, 0, st, g, V, vstride, w, n, S, first);               \
+    hipLaunchKernelGGL((gm_multiaxpy_kernel<N, SV>), grid, blk, 0, st, g, V, vstride, w, n, S, first);           \
     break;
     GM_NV_CASES(GM_AXPY)
 #undef GM_AXPY
@@ -217,7 +219,8 @@ hipError_t launch_multiaxpy(int nv, dim3 grid, dim3 blk, hipStream_t st, const G
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void gm_norm_kernel(Geom g, Field<double> w, int n_rhs, double* part) {
+template <typename S>
+__global__ __launch_bounds__(256) void gm_norm_kernel(Geom g, Field<S> w, int n_rhs, double* part) {
   GM_LANE
   double v = 0.0;
   if (valid) {
@@ -268,7 +271,8 @@ __global__ void gm_norm_finish_kernel(const double* part, int nblk, int n_rhs, G
 }
 
 // v_out = w / |w| (|w| from the state); zero if |w| = 0
-__global__ __launch_bounds__(256) void gm_scale_kernel(Geom g, Field<double> w, Field<double> vout, int n_rhs,
+template <typename SI, typename SO>
+__global__ __launch_bounds__(256) void gm_scale_kernel(Geom g, Field<SI> w, Field<SO> vout, int n_rhs,
                                                        const GmState* st) {
   GM_LANE
   if (!valid) return;
@@ -343,7 +347,8 @@ __global__ void gm_solve_kernel(GmState* st, int n_rhs) {
 }
 
 // x += sum_{j < k} y_j z_j
-__global__ __launch_bounds__(256) void gm_xupdate_kernel(Geom g, Field<double> Z, size_t zstride, Field<double> x,
+template <typename SZ>
+__global__ __launch_bounds__(256) void gm_xupdate_kernel(Geom g, Field<SZ> Z, size_t zstride, Field<double> x,
                                                          int n_rhs, const GmState* st) {
   GM_LANE
   if (!valid) return;
@@ -353,7 +358,7 @@ __global__ __launch_bounds__(256) void gm_xupdate_kernel(Geom g, Field<double> Z
   load_spinor(x, r, par, s, xx);
   for (int j = 0; j < k; ++j) {
     const cpx<double> y = {st[r].yr[j], st[r].yi[j]};
-    Field<double> zj = Z;
+    Field<SZ> zj = Z;
     zj.data += j * zstride;
     Spinor<double> zz;
     load_spinor(zj, r, par, s, zz);
@@ -381,85 +386,125 @@ using namespace mfq;
 
 namespace {
 
-struct GmBufs {
-  OwnedField<double> V, Z, w, xsave;
-  DevBuf st, part;
+template <typename F>
+struct FieldElem;
+template <typename X>
+struct FieldElem<mfq::Field<X>> {
+  using type = X;
 };
 
-struct GmCtx {
-  mfq_handle* h;
-  int n, m, use_pc;
-  GmBufs b;
-  GmState* host = nullptr;
+template <typename S>
+struct GmBufs {
+  OwnedField<S> V, Z, w;             // Arnoldi basis, preconditioned directions, A z
+  OwnedField<double> xsave, bsave;  // the CG fallback's saved solution and right-hand side
+  DevBuf st, part;
 };
 
 }  // namespace
 
 namespace mfq {
 
-// Right-preconditioned FGMRES(m) on D^+D x64 = b64 (packed FP64).
-int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
+// Right-preconditioned FGMRES(m) on D^+D x64 = b64 (packed FP64).  S is the
+// precision of the cycle: the basis, the preconditioned directions, the
+// operator inside the cycle and the network's input and output (FP64, or
+// FP32 with the links' FP32 copy); the solution, the true residual each
+// cycle restarts from and the Hessenberg entries (FP64 sums of the dot
+// products) are FP64 in both.
+template <typename S>
+int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
   const Geom& g = h->g;
   Workspace& w = h->ws;
   const int m = P->restart > 0 ? (P->restart < GM_MAXM ? P->restart : GM_MAXM) : 16;
   const bool use_pc = P->precond == MFQ_PC_PTC;
   const double tol2 = P->tol * P->tol;
-  GmBufs B;
+  GmBufs<S> B;
   auto cleanup = [&]() {
     B.V.free_all();
     B.Z.free_all();
     B.w.free_all();
     B.xsave.free_all();
+    B.bsave.free_all();
     release(B.st);
     release(B.part);
   };
-  const size_t fch = field_chunks<double>(g, n);
+  using C = typename Store<S>::chunk;
+  const size_t fch = field_chunks<S>(g, n);         // chunks of one n-RHS field in the cycle precision
+  const size_t fch64 = field_chunks<double>(g, n);  // ... and in FP64
   if (B.V.alloc(g, n * (m + 1)) || B.Z.alloc(g, n * m) || B.w.alloc(g, n) || B.xsave.alloc(g, n) ||
-      ensure(B.st, sizeof(GmState) * n) || ensure(B.part, sizeof(double) * 2 * (size_t)n * (m + 1) * ((2 * g.vh + 255) / 256))) {
+      B.bsave.alloc(g, n) || ensure(B.st, sizeof(GmState) * n) ||
+      ensure(B.part, sizeof(double) * 2 * (size_t)n * (m + 1) * ((2 * g.vh + 255) / 256))) {
     cleanup();
     return fail(MFQ_ERR_NOMEM, "FGMRES workspace");
   }
   std::vector<GmState> host(n);
   const int nblk = (2 * g.vh + 255) / 256;
   const dim3 grid(nblk, n), blk(256);
-  GmState* S = (GmState*)B.st.ptr;
+  GmState* Sg = (GmState*)B.st.ptr;
   double* part = (double*)B.part.ptr;
-  Field<double> V = B.V.view(g), Z = B.Z.view(g), W = B.w.view(g);
+  Field<S> V = B.V.view(g), Z = B.Z.view(g), W = B.w.view(g);
   Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), r64 = w.r64.view(g), t64 = w.t64.view(g);
-  auto vj = [&](Field<double> base, int j) {
-    Field<double> f = base;
+  auto vj = [&](Field<S> base, int j) {
+    Field<S> f = base;
     f.data += (size_t)j * fch;
     return f;
   };
-  Shape sh;
-  if (int rc0 = fp64_hop_shape(h, n, st, &sh)) return cleanup(), rc0;
-  HopArgs<double, double> a = hop_args<double, double>(h, links_d(h), n);
+  Shape sh64;
+  if (int rc0 = fp64_hop_shape(h, n, st, &sh64)) return cleanup(), rc0;
+  HopArgs<double, double> a64 = hop_args<double, double>(h, links_d(h), n);
+  a64.coef = -h->lat.kappa;
+  // the operator inside the cycle: D^+ D in precision S
+  Shape sh = sh64;
+  Field<S> tS;
+  Links<S> LS;
+  if constexpr (sizeof(S) == 8) {
+    tS = t64;
+    LS = links_d(h);
+  } else {
+    if (int rc0 = fp32_hop_shape(h, n, st, &sh)) return cleanup(), rc0;
+    tS = w.ts.view(g);
+    LS = links_f(h);
+  }
+  HopArgs<S, S> a = hop_args<S, S>(h, LS, n);
   a.coef = -h->lat.kappa;
-  // out = D^+ D in (FP64), t64 scratch
-  auto apply_a = [&](Field<double> in, Field<double> out) -> int {
+  auto apply_a = [&](Field<S> in, Field<S> out) -> int {
     a.in = a.self = in;
-    a.out = t64;
+    a.out = tS;
     a.dagger = 0;
     a.part = nullptr;
     a.par = 2;
-    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-    a.in = a.self = t64;
+    HIPCHK((launch_hop<S, S>(EPI_D, a, sh, st)));
+    a.in = a.self = tS;
     a.out = out;
     a.dagger = 1;
-    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
+    HIPCHK((launch_hop<S, S>(EPI_D, a, sh, st)));
     return MFQ_OK;
   };
-  auto norm_finish = [&](Field<double> f, int j, int which) -> int {
-    hipLaunchKernelGGL(gm_norm_kernel, grid, blk, 0, st, g, f, n, part);
+  auto norm_finish = [&](auto f, int j, int which) -> int {
+    hipLaunchKernelGGL((gm_norm_kernel<typename FieldElem<decltype(f)>::type>), grid, blk, 0, st, g, f, n, part);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(gm_norm_finish_kernel, dim3((n + 3) / 4), dim3(256), 0, st, part, nblk, n, S, j, which, tol2);
+    hipLaunchKernelGGL(gm_norm_finish_kernel, dim3((n + 3) / 4), dim3(256), 0, st, part, nblk, n, Sg, j, which, tol2);
     return hipGetLastError() == hipSuccess ? MFQ_OK : fail(MFQ_ERR_HIP, "gm_norm_finish");
+  };
+  // the FP64 true residual r64 = b64 - A x64
+  auto true_residual = [&]() -> int {
+    a64.in = a64.self = x64;
+    a64.out = t64;
+    a64.dagger = 0;
+    a64.part = nullptr;
+    a64.par = 2;
+    HIPCHK((launch_hop<double, double>(EPI_D, a64, sh64, st)));
+    a64.in = a64.self = t64;
+    a64.bvec = b64;
+    a64.r64 = r64;
+    a64.dagger = 1;
+    HIPCHK((launch_hop<double, double>(EPI_RES, a64, sh64, st)));
+    return MFQ_OK;
   };
   int rc;
   // x = 0, r = b, v_0 = b / |b|
-  HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, fch * sizeof(d2), st));
+  HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, fch64 * sizeof(d2), st));
   if ((rc = norm_finish(b64, 0, 1))) return cleanup(), rc;
-  hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, b64, vj(V, 0), n, S);
+  hipLaunchKernelGGL((gm_scale_kernel<double, S>), grid, blk, 0, st, g, b64, vj(V, 0), n, Sg);
   const int max_cycles = (P->max_iter + m - 1) / m;
   double prev_worst = 1e300;
   bool fell_back = false;
@@ -469,7 +514,7 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
       if (use_pc) {
         if ((rc = ptc_apply_fields(h, vj(V, j), vj(Z, j), n, st))) return cleanup(), rc;
       } else {
-        HIPCHK(hipMemcpyAsync(vj(Z, j).data, vj(V, j).data, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(vj(Z, j).data, vj(V, j).data, fch * sizeof(C), hipMemcpyDeviceToDevice, st));
       }
       if ((rc = apply_a(vj(Z, j), W))) return cleanup(), rc;
       // classical Gram-Schmidt; the second pass only where the first lost
@@ -477,33 +522,23 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
       // the other RHS)
       for (int pass = 0; pass < 2; ++pass) {
         const int first = pass == 0 ? 1 : 0;
-        HIPCHK(launch_multidot(j + 1, grid, blk, st, g, V, fch, W, n, part, first, S));
+        HIPCHK(launch_multidot<S>(j + 1, grid, blk, st, g, V, fch, W, n, part, first, Sg));
         hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 2) + 3) / 4), dim3(256), 0, st, part, nblk, j + 1,
-                           n, S, j, first);
-        HIPCHK(launch_multiaxpy(j + 1, grid, blk, st, g, V, fch, W, n, S, first));
+                           n, Sg, j, first);
+        HIPCHK(launch_multiaxpy<S>(j + 1, grid, blk, st, g, V, fch, W, n, Sg, first));
       }
       if ((rc = norm_finish(W, j, 0))) return cleanup(), rc;
-      hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, W, vj(V, j + 1), n, S);
-      hipLaunchKernelGGL(gm_givens_kernel, dim3((n + 63) / 64), dim3(64), 0, st, S, n, j, m, tol2);
+      hipLaunchKernelGGL((gm_scale_kernel<S, S>), grid, blk, 0, st, g, W, vj(V, j + 1), n, Sg);
+      hipLaunchKernelGGL(gm_givens_kernel, dim3((n + 63) / 64), dim3(64), 0, st, Sg, n, j, m, tol2);
       HIPCHK(hipGetLastError());
     }
-    hipLaunchKernelGGL(gm_solve_kernel, dim3((n + 63) / 64), dim3(64), 0, st, S, n);
-    hipLaunchKernelGGL(gm_xupdate_kernel, grid, blk, 0, st, g, Z, fch, x64, n, S);
-    // true residual r = b - A x, restart v_0 = r / |r|
-    a.in = a.self = x64;
-    a.out = t64;
-    a.dagger = 0;
-    a.par = 2;
-    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-    a.in = a.self = t64;
-    a.bvec = b64;
-    a.r64 = r64;
-    a.dagger = 1;
-    a.par = 2;
-    HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
+    hipLaunchKernelGGL(gm_solve_kernel, dim3((n + 63) / 64), dim3(64), 0, st, Sg, n);
+    hipLaunchKernelGGL((gm_xupdate_kernel<S>), grid, blk, 0, st, g, Z, fch, x64, n, Sg);
+    // true residual r = b - A x (FP64), restart v_0 = r / |r|
+    if ((rc = true_residual())) return cleanup(), rc;
     if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
-    hipLaunchKernelGGL(gm_scale_kernel, grid, blk, 0, st, g, r64, vj(V, 0), n, S);
-    HIPCHK(hipMemcpyAsync(host.data(), S, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL((gm_scale_kernel<double, S>), grid, blk, 0, st, g, r64, vj(V, 0), n, Sg);
+    HIPCHK(hipMemcpyAsync(host.data(), Sg, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool all_done = true, bad = false;
     double worst = 0.0;
@@ -534,8 +569,8 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
     bool bad = false;
     for (int r = 0; r < n; ++r) bad = bad || !isfinite(host[r].rtrue2);
     if (bad) {
-      HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, fch * sizeof(d2), st));
-      HIPCHK(hipMemcpyAsync(r64.data, b64.data, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, fch64 * sizeof(d2), st));
+      HIPCHK(hipMemcpyAsync(r64.data, b64.data, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
     }
     // tolerance for the residual system so that |b - A x| <= tol |b| for
     // every RHS: tol * min_i |b_i| / |r_i|
@@ -543,9 +578,9 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
     for (int r = 0; r < n; ++r)
       if (!bad && host[r].rtrue2 > 0 && host[r].bnorm2 > 0)
         ratio = fmin(ratio, sqrt(host[r].bnorm2 / host[r].rtrue2));
-    HIPCHK(hipMemcpyAsync(B.xsave.data.ptr, w.x64.data.ptr, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(B.w.data.ptr, w.b64.data.ptr, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, r64.data, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.xsave.data.ptr, w.x64.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.bsave.data.ptr, w.b64.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, r64.data, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
     mfq_solve_params Q = *P;
     Q.precond = MFQ_PC_NONE;
     Q.prec = MFQ_PREC_FP64;
@@ -555,22 +590,11 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
     if (rc < 0) return cleanup(), rc;
     for (int r = 0; r < n; ++r) cg_iters = cg_iters > cst[r].iters ? cg_iters : cst[r].iters;
     hipLaunchKernelGGL(gm_add_kernel, grid, blk, 0, st, g, x64, B.xsave.view(g), n);
-    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, B.w.data.ptr, fch * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, B.bsave.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
     // final FP64 true residual against the original right-hand side
-    a.in = a.self = x64;
-    a.out = t64;
-    a.dagger = 0;
-    a.part = nullptr;
-    a.par = 2;
-    HIPCHK(launch_hop<double, double>(EPI_D, a, sh, st));
-    a.in = a.self = t64;
-    a.bvec = b64;
-    a.r64 = r64;
-    a.dagger = 1;
-    a.par = 2;
-    HIPCHK(launch_hop<double, double>(EPI_RES, a, sh, st));
+    if ((rc = true_residual())) return cleanup(), rc;
     if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
-    HIPCHK(hipMemcpyAsync(host.data(), S, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(host.data(), Sg, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
     status = MFQ_FELL_BACK;
     for (int r = 0; r < n; ++r)
       if (!host[r].done) status = MFQ_NOT_CONVERGED;
@@ -586,6 +610,12 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
   }
   cleanup();
   return status;
+}
+
+// FGMRES with the cycle in FP64 (prec FP64) or FP32 (otherwise).
+int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
+  if (P->prec == MFQ_PREC_FP64) return run_fgmres_t<double>(h, n, P, st, stats);
+  return run_fgmres_t<float>(h, n, P, st, stats);
 }
 
 }  // namespace mfq

@@ -109,6 +109,9 @@ int run_fgmres(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, 
 int run_block_cg(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats);
 // the tuned launch shape of the FP64 hopping kernel for n RHS
 int fp64_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out);
+// The tuned FP32 shape (allocates the FP32 p and t fields of the workspace,
+// which it times on; t then serves as scratch of the FP32 operator).
+int fp32_hop_shape(mfq_handle* h, int n, hipStream_t st, Shape* out);
 // out = op(in) in FP64 (mfq_op); tmp is scratch for DDAGD; sh2 is the shape of
 // the both-parity launches
 int apply_op_fp64(mfq_handle* h, int op, Field<double> in, Field<double> tmp, Field<double> out, int n_rhs,
@@ -117,7 +120,8 @@ int apply_op_fp64(mfq_handle* h, int op, Field<double> in, Field<double> tmp, Fi
 int noalloc_init_current_device();
 // learned preconditioner (ptc_host.hip)
 void ptc_free(mfq_handle* h);
-int ptc_apply_fields(mfq_handle* h, Field<double> in, Field<double> out, int n, hipStream_t st);
+template <typename S>
+int ptc_apply_fields(mfq_handle* h, Field<S> in, Field<S> out, int n, hipStream_t st);
 
 template <typename S, typename SX>
 HopArgs<S, SX> hop_args(mfq_handle* h, Links<S> L, int n_rhs) {

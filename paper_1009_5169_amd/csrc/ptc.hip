@@ -542,6 +542,8 @@ hipError_t ptc_adjoint2_mx(const Geom& g, Links<float> L, Field<float> gy, Field
 
 template hipError_t ptc_forward_mx<double, double>(const Geom&, Links<float>, Field<double>, float*, Field<double>,
                                                    const void*, int, hipStream_t);
+template hipError_t ptc_forward_mx<float, float>(const Geom&, Links<float>, Field<float>, float*, Field<float>,
+                                                 const void*, int, hipStream_t);
 
 // ------------------------------------------- matrix-core weight gradients
 // dW[p][c_o][c_i] (complex 4x4 spin matrix [s_o][s_i]) is a sum over pairs

@@ -103,9 +103,11 @@ def test_bandwidth_lattice_operator(prec, tol):
     lat.close()
 
 
-def test_full_size_learned_solve_matches_oracle():
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_learned_solve_matches_oracle(prec):
     """The learned row at full size (16^3x16 SF, kappa 0.1375, 5 RHS): a
-    network trained briefly on the GPU, FGMRES(16) with it to the parity
+    network trained briefly on the GPU, FGMRES(16) with it (the cycle in FP64
+    or in FP32 with FP64 restarts) to the parity
     tolerance min(1e-10, 3e-10 / cond) (cond from the oracle's Lanczos
     estimate), every residual re-measured with the oracle's operator, and the
     first RHS's solution within 1e-9 of the oracle's own CG solution."""
@@ -121,16 +123,16 @@ def test_full_size_learned_solve_matches_oracle():
     cond = solvers.cg_cond(d.DdagD, b[:1], 150)
     tol = min(1e-10, 3e-10 / cond)  # the Lanczos estimate bounds cond from below
     note(f"{p.name}: training loss {hist[0]:.3f} -> {hist[-1]:.3f}; cond ~ {cond:.0f}, parity tol {tol:.2e}")
-    x, st, rc = lat.solve(to_dev(b), tol=tol, prec="fp64", precond="ptc", max_iter=50000)
+    x, st, rc = lat.solve(to_dev(b), tol=tol, prec=prec, precond="ptc", max_iter=50000)
     assert rc == 0, st
     x = to_host(x)
     res = [float(np.linalg.norm((b[i:i + 1] - d.DdagD(x[i:i + 1]))) / np.linalg.norm(b[i]))
            for i in range(p.n_rhs)]
-    note(f"{p.name} fgmres+ptc: iters {[s['iters'] for s in st]} oracle residuals "
+    note(f"{p.name} fgmres+ptc {prec}: iters {[s['iters'] for s in st]} oracle residuals "
          + ", ".join("%.2e" % v for v in res))
     assert max(res) <= 1.05 * tol
     x_ref, _ = solvers.cg(d.DdagD, b[:1], 1e-13)
     err = rel(x[:1], x_ref)
-    note(f"{p.name} fgmres+ptc: RHS 0 error against the oracle's CG solution {err:.2e}")
+    note(f"{p.name} fgmres+ptc {prec}: RHS 0 error against the oracle's CG solution {err:.2e}")
     assert err < 1e-9
     lat.close()

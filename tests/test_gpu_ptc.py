@@ -103,8 +103,11 @@ def _solve_check(lat, d, b, x, tol):
         assert np.linalg.norm(r[i]) / np.linalg.norm(b[i]) <= 1.05 * tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("precond", ["identity", "ptc"])
-def test_fgmres_solution_meets_tolerance(precond):
+def test_fgmres_solution_meets_tolerance(precond, prec):
+    """The cycle in FP64, or in FP32 (basis, operator, network in and out)
+    with FP64 restarts: the FP64 true residual meets 1e-10 either way."""
     dims, bc, kappa = (4, 4, 4, 8), "sf", 0.13
     u = synth.random_links(dims, bc, 0.3, 1000)
     lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
@@ -112,8 +115,8 @@ def test_fgmres_solution_meets_tolerance(precond):
     # paths): GMRES(16) converges with it as with no preconditioner
     lat.precond_init(seed=3, scale=0.02)
     b = synth.gaussian_spinors(dims, bc, 3, 2000)
-    x, stats, rc = lat.solve(to_dev(b), tol=1e-10, precond=precond, prec="fp64", max_iter=4000)
-    note(f"fgmres {precond}: rc {rc} iters {[s['iters'] for s in stats]} cycles "
+    x, stats, rc = lat.solve(to_dev(b), tol=1e-10, precond=precond, prec=prec, max_iter=4000)
+    note(f"fgmres {precond} {prec}: rc {rc} iters {[s['iters'] for s in stats]} cycles "
          f"{[s['reliable_updates'] for s in stats]}")
     # GMRES(16) converges here on its own: no hand-over to CG
     assert rc == 0 and all(s["status"] == 0 for s in stats), stats
@@ -121,8 +124,9 @@ def test_fgmres_solution_meets_tolerance(precond):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("restart", [5, 32])
-def test_fgmres_restart_lengths_meet_tolerance(restart):
+def test_fgmres_restart_lengths_meet_tolerance(restart, prec):
     """Restart lengths other than the default: every basis size 1..restart
     of the Gram-Schmidt kernels (up to the largest, 32) runs, and the solution
     meets the tolerance against the oracle's operator.  kappa = 0.11: GMRES(5)
@@ -132,9 +136,9 @@ def test_fgmres_restart_lengths_meet_tolerance(restart):
     u = synth.random_links(dims, bc, 0.3, 1000)
     lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
     b = synth.gaussian_spinors(dims, bc, 2, 2010)
-    x, stats, rc = lat.solve(to_dev(b), tol=1e-10, precond="identity", prec="fp64", max_iter=4000,
+    x, stats, rc = lat.solve(to_dev(b), tol=1e-10, precond="identity", prec=prec, max_iter=4000,
                              restart=restart)
-    note(f"fgmres restart {restart}: rc {rc} iters {[s['iters'] for s in stats]}")
+    note(f"fgmres restart {restart} {prec}: rc {rc} iters {[s['iters'] for s in stats]}")
     assert rc == 0 and all(s["status"] == 0 for s in stats), stats
     _solve_check(lat, native.NativeWilson(dims, bc, kappa, u), b, x, 1e-10)
     lat.close()
