@@ -174,14 +174,21 @@ template hipError_t launch_pack_links<_Float16>(const Geom&, const double*, h2*,
 //   B = sum_i sum_b h+[X_i(n)]_b h+[Y_i(n+mu)]_b^+ ,  h+[psi] = psi_up + e_mu psi_down
 //   M = U A - B U^+,   G = -kappa ( (M - M^+)/(2i) - Tr(...)/3 )
 // which is Eq. 3's f[x_i, y_i] summed over i, with the RHS sum taken before
-// the colour multiplications (the force is linear in the outer products).
+// the projection (the force is linear in the outer products).
+//
+// One thread per (link, half, RHS group): a workgroup is 64 sites x 2 NR
+// threads; thread y takes the half y % 2 (U A or -B U^+) for the RHS
+// y / 2, y / 2 + NR, ...; each forms its partial M, the partials meet in LDS
+// and thread y = 0 of each site adds them in y order (a fixed order, so FP64
+// results repeat bitwise), projects and stores.  Splitting the halves over
+// threads halves each thread's registers (twice the resident wavefronts).
 template <int MU>
-__device__ __forceinline__ void force_link(const Geom& g, const Links<double>& L, const Field<double>& X,
-                                           const Field<double>& Y, int n_rhs, double kappa, int par, int s,
-                                           const Coords& c, d2* out) {
+__device__ __forceinline__ void force_partial(const Geom& g, const Links<double>& L, const Field<double>& X,
+                                              const Field<double>& Y, int half, int r0, int n_rhs, int rstep, int par,
+                                              int s, const Coords& c, bool& ok, double& sgn, cpx<double> M[9]) {
   int x = c.x, y = c.y, z = c.z, t = c.t;
-  double sgn = 1.0;
-  bool ok = true;
+  sgn = 1.0;
+  ok = true;
   if constexpr (MU == 0) {
     t = c.t + 1;
     if (t == g.td) {
@@ -196,66 +203,107 @@ __device__ __forceinline__ void force_link(const Geom& g, const Links<double>& L
   } else {
     z = (c.z + 1 == g.lz) ? 0 : c.z + 1;
   }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M[k] = {0.0, 0.0};
+  if (!ok || r0 >= n_rhs) return;
+  const int sf = half_index(g, x, y, z, t);
+  const int po = 1 - par;
+  // half 0: A from X(n + mu), Y(n) with h-; half 1: B from X(n), Y(n + mu) with h+
+  const double sg = half == 0 ? -1.0 : 1.0;
+  const int xp = half == 0 ? po : par, xs_site = half == 0 ? sf : s;
+  const int yp = half == 0 ? par : po, ys_site = half == 0 ? s : sf;
+  cpx<double> AB[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) AB[k] = {0.0, 0.0};
+  for (int r = r0; r < n_rhs; r += rstep) {
+    // colour by colour: the four spin components of colour k, projected at
+    // once, so only the half spinors stay in registers
+    cpx<double> hx0[3], hx1[3], hy0[3], hy1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Spinor<double> xs, ys;  // only components 3 sp + k are filled
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        const d2 qx = X.data[X.cidx(r, xp, 3 * sp + k, xs_site)];
+        const d2 qy = Y.data[Y.cidx(r, yp, 3 * sp + k, ys_site)];
+        xs.v[3 * sp + k] = {qx.x, qx.y};
+        ys.v[3 * sp + k] = {qy.x, qy.y};
+      }
+      project<MU>(xs, sg, k, hx0[k], hx1[k]);
+      project<MU>(ys, sg, k, hy0[k], hy1[k]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        AB[3 * a + b] = AB[3 * a + b] + cjmul(hy0[b], hx0[a]) + cjmul(hy1[b], hx1[a]);
+  }
+  cpx<double> u[9];
+  load_link(L, par, MU, s, u);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      cpx<double> m = {0.0, 0.0};
+      if (half == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) m = m + cmul(u[3 * a + k], AB[3 * k + b]);  // (U A)_{ab}
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) m = m - cjmul(u[3 * b + k], AB[3 * a + k]);  // -(B U^+)_{ab}
+      }
+      M[3 * a + b] = m;
+    }
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void force_kernel(Geom g, Links<double> L, Field<double> X, Field<double> Y,
+                                                    int n_rhs, double kappa, d2* out, int n_slices) {
+  extern __shared__ __align__(16) unsigned char force_lds[];
+  cpx<double>(*part)[64][9] = reinterpret_cast<cpx<double>(*)[64][9]>(force_lds);  // [y][site][9]
+  // Workgroup b runs on XCD b % 8.  In each run of 32 workgroups, XCD x gets
+  // b = x, x + 8, x + 16, x + 24: the 4 directions of one site block, so the
+  // site's own X and Y, which all four read, meet in that XCD's L2.
+  const int b = blockIdx.x;
+  const int mu = (b >> 3) & 3;
+  // lanes walk the half-lattice sites of one parity (coalesced spinor loads)
+  const int q = ((b >> 5) * 8 + (b & 7)) * 64 + threadIdx.x;
+  const bool valid = q < 2 * g.vh;
+  const int par = valid && q >= g.vh ? 1 : 0;
+  const int s = valid ? q - par * g.vh : 0;
+  const Coords c = site_coords(g, s, par);
+  const int t = c.t;
+  cpx<double> M[9];
+  bool ok = false;
+  double sgn = 1.0;
+  const int half = threadIdx.y & 1, rstep = blockDim.y >> 1;
+  const int r0 = valid ? (int)(threadIdx.y >> 1) : n_rhs;
+  switch (mu) {
+    case 0: force_partial<0>(g, L, X, Y, half, r0, n_rhs, rstep, par, s, c, ok, sgn, M); break;
+    case 1: force_partial<1>(g, L, X, Y, half, r0, n_rhs, rstep, par, s, c, ok, sgn, M); break;
+    case 2: force_partial<2>(g, L, X, Y, half, r0, n_rhs, rstep, par, s, c, ok, sgn, M); break;
+    default: force_partial<3>(g, L, X, Y, half, r0, n_rhs, rstep, par, s, c, ok, sgn, M); break;
+  }
+  if (threadIdx.y > 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) part[threadIdx.y][threadIdx.x][k] = M[k];
+  }
+  __syncthreads();
+  if (threadIdx.y != 0 || !valid) return;
+  for (int j = 1; j < (int)blockDim.y; ++j)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) M[k] = M[k] + part[j][threadIdx.x][k];
   cpx<double> G[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) G[k] = {0.0, 0.0};
   if (ok) {
-    const int sf = half_index(g, x, y, z, t);
-    const int po = 1 - par;
-    cpx<double> A[9], B[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) A[k] = B[k] = {0.0, 0.0};
-    for (int r = 0; r < n_rhs; ++r) {
-      Spinor<double> xf, yn, xn, yf;
-      load_spinor(X, r, po, sf, xf);
-      load_spinor(Y, r, par, s, yn);
-      load_spinor(X, r, par, s, xn);
-      load_spinor(Y, r, po, sf, yf);
-      cpx<double> hx0[3], hx1[3], hy0[3], hy1[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        project<MU>(xf, -1.0, k, hx0[k], hx1[k]);
-        project<MU>(yn, -1.0, k, hy0[k], hy1[k]);
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-          A[3 * a + b] = A[3 * a + b] + cjmul(hy0[b], hx0[a]) + cjmul(hy1[b], hx1[a]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        project<MU>(xn, 1.0, k, hx0[k], hx1[k]);
-        project<MU>(yf, 1.0, k, hy0[k], hy1[k]);
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-          B[3 * a + b] = B[3 * a + b] + cjmul(hy0[b], hx0[a]) + cjmul(hy1[b], hx1[a]);
-    }
-    cpx<double> u[9];
-    load_link(L, par, MU, s, u);
-    cpx<double> M[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        cpx<double> ua = {0.0, 0.0}, bu = {0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          ua = ua + cmul(u[3 * a + k], A[3 * k + b]);
-          bu = bu + cjmul(u[3 * b + k], B[3 * a + k]);  // B_{ak} conj(U_{bk}) = (B U^+)_{ab}
-        }
-        M[3 * a + b] = sgn * (ua - bu);
-      }
-    // H = (M - M^+) / (2i): H_ab = (M_ab - conj(M_ba)) / (2i)
+    // H = (M - M^+) / (2i): H_ab = (M_ab - conj(M_ba)) / (2i), traceless part
     cpx<double> H[9];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         const cpx<double> d = {M[3 * a + b].re - M[3 * b + a].re, M[3 * a + b].im + M[3 * b + a].im};
-        H[3 * a + b] = {0.5 * d.im, -0.5 * d.re};
+        H[3 * a + b] = {0.5 * sgn * d.im, -0.5 * sgn * d.re};
       }
     const double tr3 = (H[0].re + H[4].re + H[8].re) / 3.0;
     H[0].re -= tr3;
@@ -264,43 +312,24 @@ __device__ __forceinline__ void force_link(const Geom& g, const Links<double>& L
 #pragma unroll
     for (int k = 0; k < 9; ++k) G[k] = (-kappa) * H[k];
   }
+  const long n_slice_sites = (long)g.lx * g.ly * g.lz;
+  d2* dst = out + (((long)mu * n_slices + (t + g.t0)) * n_slice_sites + c.x + (long)g.lx * (c.y + (long)g.ly * c.z)) * 9;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     d2 v;
     v.x = G[k].re;
     v.y = G[k].im;
-    out[k] = v;
-  }
-}
-
-__global__ void force_kernel(Geom g, Links<double> L, Field<double> X, Field<double> Y, int n_rhs, double kappa,
-                             d2* out, int n_slices) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // canonical dynamical site
-  const int mu = blockIdx.y;
-  if (q >= 2 * g.vh) return;
-  int x, y, z, t;
-  canon_coords(g, q, x, y, z, t);
-  const int par = (x + y + z + t + g.t0) & 1;
-  const int s = half_index(g, x, y, z, t);
-  Coords c;
-  c.x = x;
-  c.y = y;
-  c.z = z;
-  c.t = t;
-  const long n_slice_sites = (long)g.lx * g.ly * g.lz;
-  d2* dst = out + (((long)mu * n_slices + (t + g.t0)) * n_slice_sites + q % n_slice_sites) * 9;
-  switch (mu) {
-    case 0: force_link<0>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
-    case 1: force_link<1>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
-    case 2: force_link<2>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
-    default: force_link<3>(g, L, X, Y, n_rhs, kappa, par, s, c, dst); break;
+    dst[k] = v;
   }
 }
 
 hipError_t launch_force(const Geom& g, Links<double> links, Field<double> X, Field<double> Y, int n_rhs,
                         double kappa, double* force_canon, int n_link_slices, hipStream_t st) {
-  dim3 grid((2 * g.vh + 127) / 128, 4);
-  hipLaunchKernelGGL(force_kernel, grid, dim3(128), 0, st, g, links, X, Y, n_rhs, kappa, (d2*)force_canon,
+  const int nr = n_rhs < 1 ? 1 : (n_rhs < 4 ? n_rhs : 4);  // RHS groups; 2 halves each
+  const int site_blocks = (2 * g.vh + 63) / 64;
+  const dim3 grid(32 * ((site_blocks + 7) / 8)), block(64, 2 * nr);
+  const size_t lds = (size_t)2 * nr * 64 * 9 * sizeof(cpx<double>);
+  hipLaunchKernelGGL(force_kernel, grid, block, lds, st, g, links, X, Y, n_rhs, kappa, (d2*)force_canon,
                      n_link_slices);
   return hipGetLastError();
 }
