@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "5-RHS D†D solve time to 1e-10 vs plain FP64 CG; dslash HBM GB/s, % peak"
+# solve tolerance of the bench step per route, chosen for equal force accuracy
+STEP_TOL = {"full": 1e-10, "schur": 1e-11}
 HBM_PEAK_GBS = 8000.0
 HOP_FLOP = 1320  # flop of the Wilson hopping term per output site per RHS
 
@@ -129,7 +131,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "fp16"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "fp16"],
+                    help="precision of the bench step's solves (default: the fastest measured on this "
+                         "workload, see step_ms_by_route)")
+    ap.add_argument("--route", default="schur", choices=["full", "schur"],
+                    help="route of the bench step: CG on D^+D (full) or the even/odd Schur complement "
+                         "(schur, the default: the fastest measured on this workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bandwidth", action="store_true")
     ap.add_argument("--bw-dims", default="32,32,32,64")
@@ -171,9 +178,13 @@ def main():
     phi_h = p.rhs()
     lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(u).to(dev))
     phi = torch.from_numpy(phi_h).to(dev)
-    params = mfq.make_params(tol=1e-10, prec=args.prec, max_iter=20000)
+    # route S solves D X = Phi and D^+ Y = X, each to its own tolerance, so at
+    # the same tol its X, Y and force carry ~10x the error of route F's single
+    # solve on D^+D; it runs at STEP_TOL["schur"] = 1e-11, where its force
+    # matches route F's accuracy at 1e-10 (rel_err_vs_oracle checks it)
+    params = mfq.make_params(tol=STEP_TOL[args.route], prec=args.prec, max_iter=20000, route=args.route)
     torch.cuda.synchronize()
-    print(f"[bench] workload {p.name} prec={args.prec}", file=sys.stderr, flush=True)
+    print(f"[bench] workload {p.name} prec={args.prec} route={args.route}", file=sys.stderr, flush=True)
 
     def step():
         return lat.force(phi, params=params)
@@ -189,6 +200,18 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
     # the same step once more (untimed), keeping X and Y for the oracle comparison
     g_step, action_step, stats_step, _, x_step, y_step = lat.force(phi, params=params, want_xy=True)
+    # the step by every route and precision (5 timed steps each), the basis of the default
+    step_ms_by_route = {}
+    for rt in ("full", "schur"):
+        for pr_name in ("fp64", "fp32"):
+            pr_alt = mfq.make_params(tol=STEP_TOL[rt], prec=pr_name, max_iter=20000, route=rt)
+            lat.force(phi, params=pr_alt)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(5):
+                lat.force(phi, params=pr_alt)
+            torch.cuda.synchronize()
+            step_ms_by_route[f"{rt}_{pr_name}"] = round((time.perf_counter() - t) * 200, 4)
 
     # dominant kernel: the fused hopping kernel with the D epilogue of the inner
     # CG (both parities in one launch), same launch shape as in the solve,
@@ -202,7 +225,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.prec, n, shape),
                 "kernel": kernel_name(args.prec, shape), "launch_us": round(hop_ms * 1e3, 3),
-                "timing": "HIP events around 200 back-to-back launches on a nonzero field, solver launch shape",
+                "timing": "HIP events around 200 back-to-back launches on a nonzero field, solver launch shape "
+                          "(route S runs the same kernel and shape on one parity at a time)",
                 "residency": "cache-resident: %.1f MB per launch, inside the 256 MB Infinity Cache; "
                              "launch-latency bound (see roofline_hbm_lattice for the HBM-resident figure)"
                              % (per_launch / 1e6),
@@ -221,7 +245,7 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3 / reps, x, st
 
-    s_ms, x_this, st_this = solve_ms(args.prec)
+    s_ms, x_this, st_this = solve_ms("fp32")
     s64_ms, x64, st64 = solve_ms("fp64")
     s16_ms, x16, st16 = solve_ms("fp16")
     sb_ms, xb, stb = solve_ms("fp64", precond="blockcg")  # one Krylov space for all RHS
@@ -230,7 +254,7 @@ def main():
     # results the CPU-baseline leg compares with the oracle
     gpu_results = {"g": g_step.cpu().numpy(), "x": x_step.cpu().numpy(), "y": y_step.cpu().numpy(),
                    "s": list(action_step),
-                   "z": {args.prec: x_this.cpu().numpy(), "fp64": x64h, "fp16": x16.cpu().numpy(),
+                   "z": {"fp32": x_this.cpu().numpy(), "fp64": x64h, "fp16": x16.cpu().numpy(),
                          "block_cg_fp64": xb.cpu().numpy()}}
 
     out = {
@@ -239,16 +263,20 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16"}[args.prec], "data": "synthetic",
         "config": {"workload": p.name, "dims": list(p.dims), "bc": p.bc, "kappa": p.kappa,
-                   "link_eps": p.eps, "n_rhs": n, "tol": 1e-10,
-                   "step": "blocked force: batched CG on DdagD + g5 map + force + action",
-                   "inner_precision": args.prec},
+                   "link_eps": p.eps, "n_rhs": n, "tol": STEP_TOL[args.route],
+                   "step": ("blocked force (Alg. 2): D X = Phi and D^+ Y = X by CG on the even/odd Schur "
+                            "complement, odd sites rebuilt, + force + action" if args.route == "schur" else
+                            "blocked force: batched CG on DdagD + g5 map + force + action"),
+                   "route": args.route, "precision": args.prec,
+                   "step_iters": [s["iters"] for s in stats_step]},
+        "step_ms_by_route": step_ms_by_route,
         "roofline": roofline,
-        "solve_ms": {args.prec: round(s_ms, 4), "fp64": round(s64_ms, 4), "fp16": round(s16_ms, 4),
+        "solve_ms": {"fp32": round(s_ms, 4), "fp64": round(s64_ms, 4), "fp16": round(s16_ms, 4),
                      "block_cg_fp64": round(sb_ms, 4)},
-        "solve_speedup_vs_fp64_cg": round(s64_ms / s_ms, 3),
-        "iters": {args.prec: [s["iters"] for s in st_this], "fp64": [s["iters"] for s in st64],
+        "solve_speedup_fp32_vs_fp64_cg": round(s64_ms / s_ms, 3),
+        "iters": {"fp32": [s["iters"] for s in st_this], "fp64": [s["iters"] for s in st64],
                   "fp16": [s["iters"] for s in st16], "block_cg_fp64": [s["iters"] for s in stb]},
-        "solution_rel_err_vs_fp64_path": {args.prec: err(x_this), "fp16": err(x16), "block_cg_fp64": err(xb)},
+        "solution_rel_err_vs_fp64_path": {"fp32": err(x_this), "fp16": err(x16), "block_cg_fp64": err(xb)},
         "true_rel_resid_max": max(s["true_rel_resid"] for s in st_this),
     }
 
