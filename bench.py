@@ -629,14 +629,9 @@ def bench_batch(synth, mfq, torch, dev, np):
     pr = mfq.make_params(tol=1e-10, prec="fp32", max_iter=20000)
     ms, (xs, stats, rc) = _timed(lambda: batch.solve(bs, params=pr), reps=2)
     print(f"[bench] batch solve {ms:.1f} ms rc={rc}", file=sys.stderr, flush=True)
-    for lat, b in zip(lats, bs):   # untimed pass: each handle tunes its launch shape once
-        lat.solve(b, params=pr)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for lat, b in zip(lats, bs):
-        lat.solve(b, params=pr)
-    torch.cuda.synchronize()
-    t_one = (time.perf_counter() - t) * 1e3
+    # Same protocol as the batch: one untimed pass (each handle tunes its
+    # launch shape once), then the mean of two timed passes.
+    t_one, _ = _timed(lambda: [lat.solve(b, params=pr) for lat, b in zip(lats, bs)], reps=2)
     n_rhs = sum(q.n_rhs for q in probs)
     site_rhs = sum(q.n_rhs * q.dims[0] * q.dims[1] * q.dims[2] * (q.dims[3] - 1) for q in probs)
     iters = [s["iters"] for st in stats for s in st]
