@@ -1274,6 +1274,7 @@ void mfq_destroy(mfq_handle* h) {
   release(w.sums);
   release(w.bad);
   for (auto* b : {&w.md_part, &w.md_u0, &w.md_p0, &w.md_force}) release(*b);
+  for (auto* b : {&w.gm_v, &w.gm_z, &w.gm_w, &w.gm_xsave, &w.gm_bsave, &w.gm_st, &w.gm_part}) release(*b);
   if (w.host_sc) (void)hipHostFree(w.host_sc);
   release(h->links64);
   release(h->links32);

@@ -394,11 +394,13 @@ struct FieldElem<mfq::Field<X>> {
 };
 
 template <typename S>
-struct GmBufs {
-  OwnedField<S> V, Z, w;             // Arnoldi basis, preconditioned directions, A z
-  OwnedField<double> xsave, bsave;  // the CG fallback's saved solution and right-hand side
-  DevBuf st, part;
-};
+Field<S> raw_field(const DevBuf& b, const Geom& g) {
+  Field<S> f;
+  f.data = (typename Store<S>::chunk*)b.ptr;
+  f.norm = nullptr;
+  f.vh = g.vs;
+  return f;
+}
 
 }  // namespace
 
@@ -410,6 +412,11 @@ namespace mfq {
 // FP32 with the links' FP32 copy); the solution, the true residual each
 // cycle restarts from and the Hessenberg entries (FP64 sums of the dot
 // products) are FP64 in both.
+//
+// The basis and the state stay in the handle between calls, and one restart
+// cycle (m Arnoldi steps, the update of x, the FP64 true residual and the
+// next v_0) is captured once as a graph and replayed for every cycle: the
+// host only reads the per-RHS state between cycles.
 template <typename S>
 int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st, mfq_solve_stats* stats) {
   const Geom& g = h->g;
@@ -417,31 +424,21 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
   const int m = P->restart > 0 ? (P->restart < GM_MAXM ? P->restart : GM_MAXM) : 16;
   const bool use_pc = P->precond == MFQ_PC_PTC;
   const double tol2 = P->tol * P->tol;
-  GmBufs<S> B;
-  auto cleanup = [&]() {
-    B.V.free_all();
-    B.Z.free_all();
-    B.w.free_all();
-    B.xsave.free_all();
-    B.bsave.free_all();
-    release(B.st);
-    release(B.part);
-  };
   using C = typename Store<S>::chunk;
   const size_t fch = field_chunks<S>(g, n);         // chunks of one n-RHS field in the cycle precision
   const size_t fch64 = field_chunks<double>(g, n);  // ... and in FP64
-  if (B.V.alloc(g, n * (m + 1)) || B.Z.alloc(g, n * m) || B.w.alloc(g, n) || B.xsave.alloc(g, n) ||
-      B.bsave.alloc(g, n) || ensure(B.st, sizeof(GmState) * n) ||
-      ensure(B.part, sizeof(double) * 2 * (size_t)n * (m + 1) * ((2 * g.vh + 255) / 256))) {
-    cleanup();
-    return fail(MFQ_ERR_NOMEM, "FGMRES workspace");
-  }
-  std::vector<GmState> host(n);
   const int nblk = (2 * g.vh + 255) / 256;
+  if (ensure(w.gm_v, fch * (m + 1) * sizeof(C)) || (use_pc && ensure(w.gm_z, fch * m * sizeof(C))) ||
+      ensure(w.gm_w, fch * sizeof(C)) || ensure(w.gm_st, sizeof(GmState) * n) ||
+      ensure(w.gm_part, sizeof(double) * 2 * (size_t)n * (m + 1) * nblk))
+    return fail(MFQ_ERR_NOMEM, "FGMRES workspace");
+  std::vector<GmState> host(n);
   const dim3 grid(nblk, n), blk(256);
-  GmState* Sg = (GmState*)B.st.ptr;
-  double* part = (double*)B.part.ptr;
-  Field<S> V = B.V.view(g), Z = B.Z.view(g), W = B.w.view(g);
+  GmState* Sg = (GmState*)w.gm_st.ptr;
+  double* part = (double*)w.gm_part.ptr;
+  Field<S> V = raw_field<S>(w.gm_v, g), W = raw_field<S>(w.gm_w, g);
+  // without a preconditioner z_j = v_j: the directions are the basis itself
+  Field<S> Z = use_pc ? raw_field<S>(w.gm_z, g) : V;
   Field<double> b64 = w.b64.view(g), x64 = w.x64.view(g), r64 = w.r64.view(g), t64 = w.t64.view(g);
   auto vj = [&](Field<S> base, int j) {
     Field<S> f = base;
@@ -449,7 +446,7 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
     return f;
   };
   Shape sh64;
-  if (int rc0 = fp64_hop_shape(h, n, st, &sh64)) return cleanup(), rc0;
+  if (int rc0 = fp64_hop_shape(h, n, st, &sh64)) return rc0;
   HopArgs<double, double> a64 = hop_args<double, double>(h, links_d(h), n);
   a64.coef = -h->lat.kappa;
   // the operator inside the cycle: D^+ D in precision S
@@ -460,84 +457,128 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
     tS = t64;
     LS = links_d(h);
   } else {
-    if (int rc0 = fp32_hop_shape(h, n, st, &sh)) return cleanup(), rc0;
+    if (int rc0 = fp32_hop_shape(h, n, st, &sh)) return rc0;
     tS = w.ts.view(g);
     LS = links_f(h);
   }
+  if (use_pc)
+    if (int rc0 = ptc_prepare(h, n, st)) return rc0;
   HopArgs<S, S> a = hop_args<S, S>(h, LS, n);
   a.coef = -h->lat.kappa;
-  auto apply_a = [&](Field<S> in, Field<S> out) -> int {
+  auto apply_a = [&](Field<S> in, Field<S> out, hipStream_t s) -> int {
     a.in = a.self = in;
     a.out = tS;
     a.dagger = 0;
     a.part = nullptr;
     a.par = 2;
-    HIPCHK((launch_hop<S, S>(EPI_D, a, sh, st)));
+    HIPCHK((launch_hop<S, S>(EPI_D, a, sh, s)));
     a.in = a.self = tS;
     a.out = out;
     a.dagger = 1;
-    HIPCHK((launch_hop<S, S>(EPI_D, a, sh, st)));
+    HIPCHK((launch_hop<S, S>(EPI_D, a, sh, s)));
     return MFQ_OK;
   };
-  auto norm_finish = [&](auto f, int j, int which) -> int {
-    hipLaunchKernelGGL((gm_norm_kernel<typename FieldElem<decltype(f)>::type>), grid, blk, 0, st, g, f, n, part);
+  auto norm_finish = [&](auto f, int j, int which, hipStream_t s) -> int {
+    hipLaunchKernelGGL((gm_norm_kernel<typename FieldElem<decltype(f)>::type>), grid, blk, 0, s, g, f, n, part);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(gm_norm_finish_kernel, dim3((n + 3) / 4), dim3(256), 0, st, part, nblk, n, Sg, j, which, tol2);
+    hipLaunchKernelGGL(gm_norm_finish_kernel, dim3((n + 3) / 4), dim3(256), 0, s, part, nblk, n, Sg, j, which, tol2);
     return hipGetLastError() == hipSuccess ? MFQ_OK : fail(MFQ_ERR_HIP, "gm_norm_finish");
   };
   // the FP64 true residual r64 = b64 - A x64
-  auto true_residual = [&]() -> int {
+  auto true_residual = [&](hipStream_t s) -> int {
     a64.in = a64.self = x64;
     a64.out = t64;
     a64.dagger = 0;
     a64.part = nullptr;
     a64.par = 2;
-    HIPCHK((launch_hop<double, double>(EPI_D, a64, sh64, st)));
+    HIPCHK((launch_hop<double, double>(EPI_D, a64, sh64, s)));
     a64.in = a64.self = t64;
     a64.bvec = b64;
     a64.r64 = r64;
     a64.dagger = 1;
-    HIPCHK((launch_hop<double, double>(EPI_RES, a64, sh64, st)));
+    HIPCHK((launch_hop<double, double>(EPI_RES, a64, sh64, s)));
     return MFQ_OK;
   };
+  // one restart cycle, all on the device
+  auto cycle_body = [&](hipStream_t s) -> int {
+    int rc;
+    for (int j = 0; j < m; ++j) {
+      if (use_pc)
+        if ((rc = ptc_launch_fields(h, vj(V, j), vj(Z, j), n, s))) return rc;
+      if ((rc = apply_a(vj(Z, j), W, s))) return rc;
+      // classical Gram-Schmidt; the second pass only where the first lost
+      // more than 90 % of |w| (the kernels of that pass return at once for
+      // the other RHS)
+      for (int pass = 0; pass < 2; ++pass) {
+        const int first = pass == 0 ? 1 : 0;
+        HIPCHK(launch_multidot<S>(j + 1, grid, blk, s, g, V, fch, W, n, part, first, Sg));
+        hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 2) + 3) / 4), dim3(256), 0, s, part, nblk, j + 1,
+                           n, Sg, j, first);
+        HIPCHK(launch_multiaxpy<S>(j + 1, grid, blk, s, g, V, fch, W, n, Sg, first));
+      }
+      if ((rc = norm_finish(W, j, 0, s))) return rc;
+      hipLaunchKernelGGL((gm_scale_kernel<S, S>), grid, blk, 0, s, g, W, vj(V, j + 1), n, Sg);
+      hipLaunchKernelGGL(gm_givens_kernel, dim3((n + 63) / 64), dim3(64), 0, s, Sg, n, j, m, tol2);
+      HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(gm_solve_kernel, dim3((n + 63) / 64), dim3(64), 0, s, Sg, n);
+    hipLaunchKernelGGL((gm_xupdate_kernel<S>), grid, blk, 0, s, g, Z, fch, x64, n, Sg);
+    // true residual r = b - A x (FP64), restart v_0 = r / |r|
+    if ((rc = true_residual(s))) return rc;
+    if ((rc = norm_finish(r64, 0, 2, s))) return rc;
+    hipLaunchKernelGGL((gm_scale_kernel<double, S>), grid, blk, 0, s, g, r64, vj(V, 0), n, Sg);
+    HIPCHK(hipGetLastError());
+    return MFQ_OK;
+  };
+  hipGraphExec_t cycle_exec = nullptr;
+  if (P->use_graph) {
+    const PtcState* pc = use_pc ? h->ptc : nullptr;
+    std::vector<uintptr_t> key = {(uintptr_t)0x464d5247u, (uintptr_t)sizeof(S), (uintptr_t)n, (uintptr_t)m,
+                                  (uintptr_t)use_pc, (uintptr_t)V.data, (uintptr_t)Z.data, (uintptr_t)W.data,
+                                  (uintptr_t)Sg, (uintptr_t)part, (uintptr_t)b64.data, (uintptr_t)x64.data,
+                                  (uintptr_t)r64.data, (uintptr_t)t64.data, (uintptr_t)tS.data,
+                                  (uintptr_t)LS.data, (uintptr_t)a64.links.data,
+                                  (uintptr_t)(pc ? pc->chi.ptr : nullptr), (uintptr_t)(pc ? pc->ops.ptr : nullptr),
+                                  bits(tol2), bits(h->lat.kappa), (uintptr_t)sh.sb, (uintptr_t)sh.nr,
+                                  (uintptr_t)sh.xcd, (uintptr_t)sh.tc, (uintptr_t)sh.ds, (uintptr_t)sh64.sb,
+                                  (uintptr_t)sh64.nr, (uintptr_t)sh64.xcd, (uintptr_t)sh64.tc, (uintptr_t)sh64.ds};
+    for (auto& e : h->graphs)
+      if (e.key == key) cycle_exec = e.exec;
+    if (!cycle_exec) {
+      if (h->graphs.size() >= 24) drop_graphs(h);
+      GraphEntry e;
+      e.key = key;
+      HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      const int rc2 = cycle_body(h->cap_stream);
+      hipError_t ec = hipStreamEndCapture(h->cap_stream, &e.graph);
+      if (rc2 != MFQ_OK) {
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+        return rc2;
+      }
+      HIPCHK(ec);
+      if ((ec = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(e.graph);
+        return fail_hip(ec, "FGMRES cycle graph");
+      }
+      h->graphs.push_back(e);
+      cycle_exec = e.exec;
+    }
+  }
   int rc;
   // x = 0, r = b, v_0 = b / |b|
   HIPCHK(hipMemsetAsync(w.x64.data.ptr, 0, fch64 * sizeof(d2), st));
-  if ((rc = norm_finish(b64, 0, 1))) return cleanup(), rc;
+  if ((rc = norm_finish(b64, 0, 1, st))) return rc;
   hipLaunchKernelGGL((gm_scale_kernel<double, S>), grid, blk, 0, st, g, b64, vj(V, 0), n, Sg);
   const int max_cycles = (P->max_iter + m - 1) / m;
   double prev_worst = 1e300;
   bool fell_back = false;
   int status = MFQ_OK;
   for (int cycle = 0;; ++cycle) {
-    for (int j = 0; j < m; ++j) {
-      if (use_pc) {
-        if ((rc = ptc_apply_fields(h, vj(V, j), vj(Z, j), n, st))) return cleanup(), rc;
-      } else {
-        HIPCHK(hipMemcpyAsync(vj(Z, j).data, vj(V, j).data, fch * sizeof(C), hipMemcpyDeviceToDevice, st));
-      }
-      if ((rc = apply_a(vj(Z, j), W))) return cleanup(), rc;
-      // classical Gram-Schmidt; the second pass only where the first lost
-      // more than 90 % of |w| (the kernels of that pass return at once for
-      // the other RHS)
-      for (int pass = 0; pass < 2; ++pass) {
-        const int first = pass == 0 ? 1 : 0;
-        HIPCHK(launch_multidot<S>(j + 1, grid, blk, st, g, V, fch, W, n, part, first, Sg));
-        hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 2) + 3) / 4), dim3(256), 0, st, part, nblk, j + 1,
-                           n, Sg, j, first);
-        HIPCHK(launch_multiaxpy<S>(j + 1, grid, blk, st, g, V, fch, W, n, Sg, first));
-      }
-      if ((rc = norm_finish(W, j, 0))) return cleanup(), rc;
-      hipLaunchKernelGGL((gm_scale_kernel<S, S>), grid, blk, 0, st, g, W, vj(V, j + 1), n, Sg);
-      hipLaunchKernelGGL(gm_givens_kernel, dim3((n + 63) / 64), dim3(64), 0, st, Sg, n, j, m, tol2);
-      HIPCHK(hipGetLastError());
+    if (cycle_exec) {
+      HIPCHK(hipGraphLaunch(cycle_exec, st));
+    } else if ((rc = cycle_body(st))) {
+      return rc;
     }
-    hipLaunchKernelGGL(gm_solve_kernel, dim3((n + 63) / 64), dim3(64), 0, st, Sg, n);
-    hipLaunchKernelGGL((gm_xupdate_kernel<S>), grid, blk, 0, st, g, Z, fch, x64, n, Sg);
-    // true residual r = b - A x (FP64), restart v_0 = r / |r|
-    if ((rc = true_residual())) return cleanup(), rc;
-    if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
-    hipLaunchKernelGGL((gm_scale_kernel<double, S>), grid, blk, 0, st, g, r64, vj(V, 0), n, Sg);
     HIPCHK(hipMemcpyAsync(host.data(), Sg, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool all_done = true, bad = false;
@@ -566,6 +607,8 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
   if (fell_back) {
     // CG on the remaining residual, A e = r with r = b - A x, then x += e.
     // If the preconditioned solve produced NaN, CG starts again from x = 0.
+    if (ensure(w.gm_xsave, fch64 * sizeof(d2)) || ensure(w.gm_bsave, fch64 * sizeof(d2)))
+      return fail(MFQ_ERR_NOMEM, "FGMRES fallback workspace");
     bool bad = false;
     for (int r = 0; r < n; ++r) bad = bad || !isfinite(host[r].rtrue2);
     if (bad) {
@@ -578,8 +621,8 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
     for (int r = 0; r < n; ++r)
       if (!bad && host[r].rtrue2 > 0 && host[r].bnorm2 > 0)
         ratio = fmin(ratio, sqrt(host[r].bnorm2 / host[r].rtrue2));
-    HIPCHK(hipMemcpyAsync(B.xsave.data.ptr, w.x64.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(B.bsave.data.ptr, w.b64.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.gm_xsave.ptr, w.x64.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.gm_bsave.ptr, w.b64.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(w.b64.data.ptr, r64.data, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
     mfq_solve_params Q = *P;
     Q.precond = MFQ_PC_NONE;
@@ -587,13 +630,13 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
     Q.tol = fmax(fmin(P->tol * ratio, 0.5), 1e-15);
     std::vector<mfq_solve_stats> cst(n);
     rc = solve_packed(h, n, &Q, st, cst.data());
-    if (rc < 0) return cleanup(), rc;
+    if (rc < 0) return rc;
     for (int r = 0; r < n; ++r) cg_iters = cg_iters > cst[r].iters ? cg_iters : cst[r].iters;
-    hipLaunchKernelGGL(gm_add_kernel, grid, blk, 0, st, g, x64, B.xsave.view(g), n);
-    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, B.bsave.data.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(gm_add_kernel, grid, blk, 0, st, g, x64, raw_field<double>(w.gm_xsave, g), n);
+    HIPCHK(hipMemcpyAsync(w.b64.data.ptr, w.gm_bsave.ptr, fch64 * sizeof(d2), hipMemcpyDeviceToDevice, st));
     // final FP64 true residual against the original right-hand side
-    if ((rc = true_residual())) return cleanup(), rc;
-    if ((rc = norm_finish(r64, 0, 2))) return cleanup(), rc;
+    if ((rc = true_residual(st))) return rc;
+    if ((rc = norm_finish(r64, 0, 2, st))) return rc;
     HIPCHK(hipMemcpyAsync(host.data(), Sg, sizeof(GmState) * n, hipMemcpyDeviceToHost, st));
     status = MFQ_FELL_BACK;
     for (int r = 0; r < n; ++r)
@@ -608,7 +651,6 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
       stats[r].status = host[r].done ? (fell_back ? MFQ_FELL_BACK : MFQ_OK) : MFQ_NOT_CONVERGED;
     }
   }
-  cleanup();
   return status;
 }
 

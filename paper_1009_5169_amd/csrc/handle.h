@@ -20,6 +20,10 @@ struct Workspace {
   OwnedField<_Float16> rh, ph, th;
   DevBuf part, sc, sums, bad;
   DevBuf md_part, md_u0, md_p0, md_force;  // molecular dynamics (md.hip)
+  // FGMRES (fgmres.hip): basis, preconditioned directions, A z, the CG
+  // fallback's saved x and b, per-RHS state, partial sums; kept between calls
+  // so that a captured cycle can be replayed by the next solve
+  DevBuf gm_v, gm_z, gm_w, gm_xsave, gm_bsave, gm_st, gm_part;
   int cap_part = 0;  // RHS capacity of the partial-sum slots
   int nblk_max = 0;
   CgScalars* host_sc = nullptr;
@@ -122,6 +126,12 @@ int noalloc_init_current_device();
 void ptc_free(mfq_handle* h);
 template <typename S>
 int ptc_apply_fields(mfq_handle* h, Field<S> in, Field<S> out, int n, hipStream_t st);
+// the same in two parts: the weight operands and the n-RHS scratch made
+// ready (may allocate), then the launches alone (nothing allocated: safe
+// inside a graph capture once ptc_prepare has run for n)
+int ptc_prepare(mfq_handle* h, int n, hipStream_t st);
+template <typename S>
+int ptc_launch_fields(mfq_handle* h, Field<S> in, Field<S> out, int n, hipStream_t st);
 
 template <typename S, typename SX>
 HopArgs<S, SX> hop_args(mfq_handle* h, Links<S> L, int n_rhs) {

@@ -144,6 +144,37 @@ def test_fgmres_restart_lengths_meet_tolerance(restart, prec):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("precond", ["identity", "ptc"])
+def test_fgmres_graph_replays_match_eager(precond, prec):
+    """One restart cycle is captured as a graph and replayed for every cycle
+    and by later solves on the same handle.  The reductions have a fixed
+    order, so the replays give the eager cycle's solution bit for bit: three
+    solves in a row (the third with other right-hand sides), each against an
+    eager solve of the same system, with eager work and synchronisations in
+    between, and every solution against the oracle's operator."""
+    dims, bc, kappa = (4, 4, 4, 8), "sf", 0.13
+    u = synth.random_links(dims, bc, 0.3, 1000)
+    lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
+    lat.precond_init(seed=3, scale=0.02)
+    op = native.NativeWilson(dims, bc, kappa, u)
+    bs = [synth.gaussian_spinors(dims, bc, 3, 2000), synth.gaussian_spinors(dims, bc, 3, 2000),
+          synth.gaussian_spinors(dims, bc, 3, 2002)]
+    for k, b in enumerate(bs):
+        xg, sg, rcg = lat.solve(to_dev(b), tol=1e-10, precond=precond, prec=prec, max_iter=4000, use_graph=True)
+        xg = to_host(xg)
+        xe, se, rce = lat.solve(to_dev(b), tol=1e-10, precond=precond, prec=prec, max_iter=4000, use_graph=False)
+        xe = to_host(xe)
+        note(f"fgmres graph {precond} {prec} solve {k}: rc {rcg}/{rce} iters {[s['iters'] for s in sg]}")
+        assert rcg == 0 and rce == 0, (sg, se)
+        assert [s["iters"] for s in sg] == [s["iters"] for s in se]
+        assert np.array_equal(xg, xe)
+        r = b - op.DdagD(xg)
+        for i in range(b.shape[0]):
+            assert np.linalg.norm(r[i]) / np.linalg.norm(b[i]) <= 1.05e-10
+    lat.close()
+
+
 def test_bad_network_falls_back_to_cg():
     dims, bc, kappa = (4, 4, 4, 4), "sf", 0.125
     u = synth.random_links(dims, bc, 0.3, 1000)
