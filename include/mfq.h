@@ -120,7 +120,10 @@ typedef enum { MFQ_ROUTE_FULL = 0, MFQ_ROUTE_SCHUR = 1 } mfq_route;
  * the learned parallel-transport network, with CG as the fallback when a
  * cycle stagnates or breaks down (status MFQ_FELL_BACK); IDENTITY is the same
  * GMRES without preconditioner (the reference the network is measured
- * against).  BLOCKCG is block conjugate gradients on D^+D: the n_rhs (<= 8)
+ * against).  FGMRES keeps its basis (restart + 1 fields of n_rhs RHS, plus
+ * restart directions with PTC, in the cycle's precision) in the handle
+ * between calls, freed by mfq_destroy; with use_graph one restart cycle is
+ * captured once and replayed.  BLOCKCG is block conjugate gradients on D^+D: the n_rhs (<= 8)
  * right-hand sides share one Krylov space (the CG counterpart of the block
  * Krylov solvers of Sec. 3.1); FP64 only (prec must be MFQ_PREC_FP64, else
  * MFQ_ERR_ARG), every iteration is one D^+D on all RHS plus n x n complex
