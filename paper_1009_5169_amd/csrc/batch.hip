@@ -530,7 +530,13 @@ int batch_tune(mfq_batch* B, hipStream_t st) {
     HIPCHK(hipEventSynchronize(B->ev1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, B->ev0, B->ev1));
-    if (ms < best * 0.97f) {
+    // the timing covers one phase with every tile live; a larger grid must
+    // win it by 10 % (by 3 % at an equal or smaller grid), since the tail of
+    // a batch, where few lattices are left, favours fewer workgroups
+    // (64-lattice workload: 2186 ms at 256 and 512 workgroups, 2248 ms at
+    // 1024, which had won this timing by more than 3 %)
+    const float margin = cands[c & 3] > best_grid ? 0.90f : 0.97f;
+    if (ms < best * margin) {
       best = ms;
       best_grid = cands[c & 3];
       best_split = c >> 2;
