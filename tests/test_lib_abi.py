@@ -54,3 +54,41 @@ def test_batch_workload_recipe():
     assert len({p.dims for p in probs}) == 3
     assert all(1 <= p.n_rhs <= 8 and 0.12 <= p.kappa <= 0.135 and p.bc == "sf" for p in probs)
     assert len({p.link_seed for p in probs}) == 64
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmfq.so not built")
+@pytest.mark.parametrize("dims,bc,kappa,why", [
+    ((4, 4, 4, 5), 0, 0.125, "even"),
+    ((4, 4, 4, 2), 0, 0.125, "T >= 4"),
+    ((4, 4, 4, 4), 0, 0.25, "kappa"),
+    ((4, 4, 4, 4), 7, 0.125, "boundary"),
+    ((128, 128, 128, 24), 1, 0.125, "volume too large"),
+    ((2, 2, 4096, 2560), 1, 0.125, "2^31"),
+    ((4, 4, 4, 4), 0, 0.125, "links_dev is NULL"),
+])
+def test_create_rejects_bad_lattices_on_the_host(dims, bc, kappa, why):
+    """mfq_create checks the lattice before it touches the device: odd or too
+    small extents, kappa outside (0, 0.25), an unknown boundary, more than
+    4.4e7 sites (one FP64 field of a (RHS, parity) must stay under 4 GiB for
+    its buffer resource), and (volume / 2) * max(Lx / 2, Ly, Lz) >= 2^31 (the
+    division-free site coordinates are exact below it); the last case is a
+    valid lattice whose link pointer is NULL.  All return MFQ_ERR_ARG with a
+    message, and no handle."""
+    class Lattice(ctypes.Structure):  # mfq_lattice
+        _fields_ = [("dims", ctypes.c_int * 4), ("bc", ctypes.c_int), ("kappa", ctypes.c_double)]
+
+    lib = ctypes.CDLL(LIB)
+    lib.mfq_create.restype = ctypes.c_int
+    lib.mfq_create.argtypes = [ctypes.POINTER(Lattice), ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p)]
+    lib.mfq_last_error.restype = ctypes.c_char_p
+    lat = Lattice()
+    for d in range(4):
+        lat.dims[d] = dims[d]
+    lat.bc = bc
+    lat.kappa = kappa
+    out = ctypes.c_void_p(12345)
+    rc = lib.mfq_create(ctypes.byref(lat), None, None, ctypes.byref(out))
+    assert rc == -1
+    assert not out.value
+    assert why in lib.mfq_last_error().decode()
