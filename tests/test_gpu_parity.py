@@ -395,6 +395,12 @@ def test_invalid_inputs_raise():
         mfq.Lattice(dims, bc, 0.125, to_dev(bad))
     with pytest.raises(mfq.MfqError):
         mfq.Lattice(dims, bc, 0.3, to_dev(u))
+    # no right-hand sides: the library refuses n_rhs = 0 with an error
+    empty = to_dev(synth.gaussian_spinors(dims, bc, 1, 5)[:0])
+    for call in (lambda: lat.solve(empty, tol=1e-10), lambda: lat.dslash("D", empty)):
+        with pytest.raises(mfq.MfqError) as e:
+            call()
+        assert e.value.code == -1
     lat.close()
 
 
