@@ -103,6 +103,26 @@ def test_bandwidth_lattice_operator(prec, tol):
     lat.close()
 
 
+@pytest.mark.parametrize("dims,n_rhs", [((32, 32, 32, 64), 5), ((48, 48, 48, 48), 1)],
+                         ids=["32x32x32x64-5rhs", "48x48x48x48-1rhs"])
+def test_bandwidth_lattice_operator_as_timed(dims, n_rhs):
+    """D in FP32 on the bandwidth runs the bench reports beyond one RHS on
+    32^3x64: the HBM-resident roofline configuration (32^3x64, 5 RHS, the
+    tuned 5-RHS shape) and the 48^3x48 lattice, against the compiled oracle
+    over every site and RHS."""
+    import bench
+    u = bench.bandwidth_links(dims, synth, np)
+    lat = mfq.Lattice(dims, "periodic", bench.BANDWIDTH_KAPPA, to_dev(u))
+    x = synth.gaussian_spinors(dims, "periodic", n_rhs, 2610)
+    got = to_host(lat.dslash("D", to_dev(x), prec="fp32"))
+    want = native.NativeWilson(dims, "periodic", bench.BANDWIDTH_KAPPA, u).D(x)
+    for i in range(n_rhs):
+        err = rel(got[i], want[i])
+        note(f"{dims} fp32 D rhs {i} (shape {lat.hop_shape('fp32', n_rhs)}): rel err {err:.2e}")
+        assert err < 2e-6
+    lat.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_full_size_learned_solve_matches_oracle(prec):
     """The learned row at full size (16^3x16 SF, kappa 0.1375, 5 RHS): a
