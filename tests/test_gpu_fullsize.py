@@ -103,23 +103,41 @@ def test_bandwidth_lattice_operator(prec, tol):
     lat.close()
 
 
-@pytest.mark.parametrize("dims,n_rhs", [((32, 32, 32, 64), 5), ((48, 48, 48, 48), 1)],
-                         ids=["32x32x32x64-5rhs", "48x48x48x48-1rhs"])
-def test_bandwidth_lattice_operator_as_timed(dims, n_rhs):
-    """D in FP32 on the bandwidth runs the bench reports beyond one RHS on
-    32^3x64: the HBM-resident roofline configuration (32^3x64, 5 RHS, the
-    tuned 5-RHS shape) and the 48^3x48 lattice, against the compiled oracle
+# every bandwidth run the benchmark reports besides the 1-RHS FP64 / FP32 cases
+# above: lattice, boundary, precision, RHS, tolerance of the relative error
+# (FP16 storage rounds the input and the output to 11 significant bits: 2 x 2^-11)
+BANDWIDTH_RUNS = [
+    ((32, 32, 32, 64), "periodic", "fp64", 5, 1e-13),
+    ((32, 32, 32, 64), "periodic", "fp64", 8, 1e-13),
+    ((32, 32, 32, 64), "periodic", "fp32", 5, 2e-6),
+    ((32, 32, 32, 64), "periodic", "fp32", 8, 2e-6),
+    ((32, 32, 32, 64), "periodic", "fp16", 1, 1e-3),
+    ((32, 32, 32, 64), "periodic", "fp16", 5, 1e-3),
+    ((32, 32, 32, 64), "periodic", "fp16", 8, 1e-3),
+    ((48, 48, 48, 48), "periodic", "fp32", 1, 2e-6),
+    ((48, 48, 48, 48), "periodic", "fp32", 5, 2e-6),
+    ((32, 32, 32, 64), "sf", "fp32", 5, 2e-6),
+]
+
+
+@pytest.mark.parametrize("dims,bc,prec,n_rhs,tol", BANDWIDTH_RUNS,
+                         ids=[f"{'x'.join(map(str, c[0]))}-{c[1]}-{c[2]}-{c[3]}rhs" for c in BANDWIDTH_RUNS])
+def test_bandwidth_lattice_operator_as_timed(dims, bc, prec, n_rhs, tol):
+    """D on the benchmark's bandwidth lattices in the launch shape it times
+    (the tuned shape for that precision and RHS count, e.g. the 5-RHS FP32
+    shape of the HBM-resident roofline entry), against the compiled oracle
     over every site and RHS."""
     import bench
-    u = bench.bandwidth_links(dims, synth, np)
-    lat = mfq.Lattice(dims, "periodic", bench.BANDWIDTH_KAPPA, to_dev(u))
-    x = synth.gaussian_spinors(dims, "periodic", n_rhs, 2610)
-    got = to_host(lat.dslash("D", to_dev(x), prec="fp32"))
-    want = native.NativeWilson(dims, "periodic", bench.BANDWIDTH_KAPPA, u).D(x)
+    u = bench.bandwidth_links(dims, synth, np, bc)
+    lat = mfq.Lattice(dims, bc, bench.BANDWIDTH_KAPPA, to_dev(u))
+    x = synth.gaussian_spinors(dims, bc, n_rhs, 2610)
+    got = to_host(lat.dslash("D", to_dev(x), prec=prec))
+    want = native.NativeWilson(dims, bc, bench.BANDWIDTH_KAPPA, u).D(x)
+    shape = lat.hop_shape(prec, n_rhs)
     for i in range(n_rhs):
         err = rel(got[i], want[i])
-        note(f"{dims} fp32 D rhs {i} (shape {lat.hop_shape('fp32', n_rhs)}): rel err {err:.2e}")
-        assert err < 2e-6
+        note(f"{dims} {bc} {prec} D rhs {i} (shape {shape}): rel err {err:.2e}")
+        assert err < tol
     lat.close()
 
 
