@@ -270,10 +270,14 @@ def main():
                    "route": args.route, "precision": args.prec,
                    "step_iters": [s["iters"] for s in stats_step]},
         "step_ms_by_route": step_ms_by_route,
+        # the timed step against the same step by plain FP64 CG (route F: one CG
+        # on D^+D to 1e-10 + g5 map), both at the same force error vs the oracle
+        "step_speedup_vs_plain_fp64_cg": round(step_ms_by_route["full_fp64"] / ms_per_step, 3),
         "roofline": roofline,
         "solve_ms": {"fp32": round(s_ms, 4), "fp64": round(s64_ms, 4), "fp16": round(s16_ms, 4),
                      "block_cg_fp64": round(sb_ms, 4)},
         "solve_speedup_fp32_vs_fp64_cg": round(s64_ms / s_ms, 3),
+        "solve_speedup_fp16_vs_fp64_cg": round(s64_ms / s16_ms, 3),
         "iters": {"fp32": [s["iters"] for s in st_this], "fp64": [s["iters"] for s in st64],
                   "fp16": [s["iters"] for s in st16], "block_cg_fp64": [s["iters"] for s in stb]},
         "solution_rel_err_vs_fp64_path": {"fp32": err(x_this), "fp16": err(x16), "block_cg_fp64": err(xb)},
