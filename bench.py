@@ -522,9 +522,9 @@ def bench_learned(synth, mfq, torch, dev, np, keep):
 def bench_routes(synth, mfq, torch, dev, np):
     """Route F (one CG on D^+D over every site, then X = D^+ Y) against route S
     (D X = Phi and D^+ Y = X, each by CG on the even/odd Schur complement) for
-    the blocked force on the 8^3x8 and 16^3x16 workloads, FP64 and FP32
-    inner, to 1e-10; and the even/odd action variant (one CG on D^+D^ over the
-    even sites).  Forces are compared with the route F force of the same
+    the blocked force on the 8^3x8 and 16^3x16 workloads, FP64, FP32 and FP16
+    storage inner, to 1e-10; and the even/odd action variant (one CG on D^+D^
+    over the even sites).  Forces are compared with the route F force of the same
     precision (the two routes compute the same definition)."""
     res = {}
     for p in (synth.CONFIG_1, synth.CONFIG_2):
@@ -532,7 +532,7 @@ def bench_routes(synth, mfq, torch, dev, np):
         lat = mfq.Lattice(p.dims, p.bc, p.kappa, torch.from_numpy(p.links()).to(dev))
         phi = torch.from_numpy(p.rhs()).to(dev)
         row = {"workload": p.name, "tol": 1e-10}
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "fp16"):
             gs = {}
             for route in ("full", "schur"):
                 pr = mfq.make_params(tol=1e-10, prec=prec, max_iter=50000, route=route)
