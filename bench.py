@@ -203,7 +203,7 @@ def main():
     # the step by every route and precision (5 timed steps each), the basis of the default
     step_ms_by_route = {}
     for rt in ("full", "schur"):
-        for pr_name in ("fp64", "fp32"):
+        for pr_name in ("fp64", "fp32", "fp16"):
             pr_alt = mfq.make_params(tol=STEP_TOL[rt], prec=pr_name, max_iter=20000, route=rt)
             lat.force(phi, params=pr_alt)
             torch.cuda.synchronize()
