@@ -593,9 +593,10 @@ def bench_paper_solvers(synth, mfq, torch, dev, np):
 
 def bench_hmc(synth, mfq, torch, dev, np):
     """One leapfrog HMC trajectory on the GPU (tau = 0.5, 10 steps, 11 force
-    evaluations) on the 8^3x8 SF 5-pseudo-fermion workload with FP32 inner
-    solves to 1e-10: time per trajectory, Delta H (FP64) and the decision with
-    the draw u = 0.5.  The pseudo-fermion action only (no gauge action)."""
+    evaluations) on the 8^3x8 SF 5-pseudo-fermion workload, forces by route F
+    (FP64 or FP32 inner solves) or route S (FP64): time per trajectory, Delta H
+    (FP64) and the decision with the draw u = 0.5.  The pseudo-fermion action
+    only (no gauge action)."""
     p = synth.CONFIG_1
     print(f"[bench] row hmc {p.name}", file=sys.stderr, flush=True)
     u = p.links()
@@ -604,15 +605,17 @@ def bench_hmc(synth, mfq, torch, dev, np):
     # momenta on every link: the library moves only the links that enter D
     pm = synth.gaussian_momentum_matrices(p.dims, p.bc, 4001)
     out = {"workload": p.name, "tau": 0.5, "n_steps": 10}
-    for prec in ("fp64", "fp32"):
+    # route F (tol 1e-10) in FP64 and FP32, and route S in FP64 at the bench
+    # step's tolerance (its force as accurate as route F's)
+    for key, prec, route in (("fp64", "fp64", "full"), ("fp32", "fp32", "full"), ("schur_fp64", "fp64", "schur")):
         links = torch.from_numpy(u).to(dev)
         mom = torch.from_numpy(pm).to(dev)
         lat.update_links(links)
         t = time.perf_counter()
-        r, rc = lat.hmc_trajectory(links, mom, phi, 0.5, 10, 0.5, tol=1e-10, prec=prec)
+        r, rc = lat.hmc_trajectory(links, mom, phi, 0.5, 10, 0.5, tol=STEP_TOL[route], prec=prec, route=route)
         torch.cuda.synchronize()
-        out[prec] = {"ms": round((time.perf_counter() - t) * 1e3, 2), "rc": rc, "delta_h": r["delta_h"],
-                     "accepted": r["accepted"], "solver_iters": r["solver_iters"], "force_evals": r["force_evals"]}
+        out[key] = {"ms": round((time.perf_counter() - t) * 1e3, 2), "rc": rc, "delta_h": r["delta_h"],
+                    "accepted": r["accepted"], "solver_iters": r["solver_iters"], "force_evals": r["force_evals"]}
     lat.close()
     return out
 

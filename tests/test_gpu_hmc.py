@@ -74,8 +74,10 @@ def test_kinetic_kick_and_link_update(case):
     lat.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_trajectory_matches_oracle_leapfrog(prec):
+@pytest.mark.parametrize("prec,route", [("fp64", "full"), ("fp32", "full"), ("fp64", "schur"), ("fp32", "schur")])
+def test_trajectory_matches_oracle_leapfrog(prec, route):
+    """The GPU leapfrog against the oracle's, with the forces by route F or by
+    route S (the paper's D X = Phi, D^+ Y = X through the Schur complement)."""
     dims, bc, kappa = TINY
     u, phi, pa = setup(dims, bc, kappa)
     md = hmc.FermionMD(dims, bc, kappa, phi)
@@ -84,9 +86,10 @@ def test_trajectory_matches_oracle_leapfrog(prec):
     dh_ref = md.hamiltonian(u_ref, p_ref) - md.hamiltonian(u, pa)
     lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
     links, mom = to_dev(u), to_dev(fmod.coefficients_to_matrix(pa))
-    res, rc = lat.hmc_trajectory(links, mom, to_dev(phi), tau, n, 0.0, tol=1e-13, prec=prec, max_iter=5000)
+    res, rc = lat.hmc_trajectory(links, mom, to_dev(phi), tau, n, 0.0, tol=1e-13, prec=prec, max_iter=5000,
+                                 route=route)
     assert rc == 0 and res["accepted"] == 1 and res["force_evals"] == n + 1
-    note(f"trajectory {prec}: dH gpu {res['delta_h']:.10e} oracle {dh_ref:.10e}")
+    note(f"trajectory {prec} {route}: dH gpu {res['delta_h']:.10e} oracle {dh_ref:.10e}")
     assert abs(res["delta_h"] - dh_ref) < 1e-7 * abs(dh_ref) + 1e-10
     assert np.abs(to_host(links) - u_ref).max() < 1e-11
     assert np.abs(fmod.matrix_to_coefficients(to_host(mom)) - p_ref).max() < 1e-10
