@@ -56,7 +56,7 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* part_a, d
   __syncthreads();
 }
 
-// <v_l, w> for l < NV, and |w|^2 as entry NV: partials
+// <v_l, w> for l < NV, and with `first` also |w|^2 as entry NV: partials
 // part[((r * (NV + 1) + l) * nblk + blk) * 2 + {re, im}].  All NV dot
 // products accumulate in registers (the basis vectors' loads issue together)
 // and meet in one workgroup reduction.  The second pass runs only for the RHS
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<S> V, si
   }
   __syncthreads();
   const int i = threadIdx.x;
-  if (i <= 2 * NV) {
+  if (i < 2 * NV || (first && i == 2 * NV)) {
     const double v = ((ws[0][i] + ws[1][i]) + ws[2][i]) + ws[3][i];
     const int l = i / 2;  // i = 2 NV gives l = NV, the |w|^2 entry
     double* base = part + (((long)r * (NV + 1) + l) * gridDim.x + blockIdx.x) * 2;
@@ -113,11 +113,11 @@ __global__ __launch_bounds__(256) void gm_multidot_kernel(Geom g, Field<S> V, si
 }
 
 // coefficients c_l = sum of partials; H(:, j) += c (accumulate over passes).
-// One wavefront per (RHS, l); l = nv reduces |w|^2 (of w before this pass).
+// One wavefront per (RHS, l); the first pass also reduces |w|^2 (l = nv).
 __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int n_rhs, GmState* st, int j, int first) {
   const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  const int nl = nv + 1;
+  const int nl = nv + (first ? 1 : 0);
   if (w >= n_rhs * nl) return;
   const int r = w / nl, l = w % nl;
   if (!first && !st[r].reorth) return;
@@ -131,7 +131,7 @@ __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int 
   im = wave_sum(im);
   if (lane == 0) {
     GmState& S = st[r];
-    if (l == nv) {  // |w|^2 before this pass's projection
+    if (l == nv) {  // first pass: |w|^2 before the projection
       S.w2 = re;
       return;
     }
@@ -148,37 +148,25 @@ __global__ void gm_dots_finish_kernel(const double* part, int nblk, int nv, int 
   }
 }
 
-// w' = w - sum_l c_l v_l (l < NV, unrolled so that the loads issue together),
-// and with it the next basis vector v_{j+1} = w' / |w'|, its norm taken from
-// the pass's own sums: |w'|^2 = |w|^2 - sum |c_l|^2 (orthonormal v_l; every
-// workgroup forms it in the same order, workgroup 0 stores it as H(j+1, j)).
-// After the first pass a second one is needed when the projection removed
-// more than 99 % of |w|^2 (|w'| < 0.1 |w|): cancellation has then eaten the
-// orthogonality, and the difference above would lose most of its digits, so
-// the pass writes the unnormalised w' back to w instead, and the second pass
-// (its |w'|^2 summed afresh from the stored w') normalises.  (Kahan's 0.7
-// fires on nearly every step once the preconditioner is good, since A z_j then
-// lies almost in the span of the basis; each cycle restarts from the FP64
-// true residual, so lost orthogonality could only cost iterations.)  The flag
-// is written by workgroup 0 and read only by later launches.
+// w -= sum_l c_l v_l (l < NV, unrolled so that the loads issue together).
+// After the first pass, workgroup 0 of each RHS decides whether the second
+// pass is needed: the projected norm |w'|^2 = |w|^2 - sum |c_l|^2 below
+// 1 % of |w|^2 (|w'| < 0.1 |w|) means cancellation has eaten the
+// orthogonality and the pass is repeated.  (Kahan's 0.7 fires on nearly
+// every step once the preconditioner is good, since A z_j then lies almost
+// in the span of the basis; each cycle restarts from the FP64 true residual,
+// so lost orthogonality could only cost iterations.)  No other workgroup of
+// this launch reads the flag.
 template <int NV, typename S>
 __global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<S> V, size_t vstride, Field<S> w,
-                                                           Field<S> vnext, int n_rhs, GmState* st, int first,
-                                                           int j) {
+                                                           int n_rhs, GmState* st, int first) {
   GM_LANE
   if (!first && !st[r].reorth) return;
-  double c2 = 0.0;
-  for (int l = 0; l < NV; ++l) c2 += st[r].cr[l] * st[r].cr[l] + st[r].ci[l] * st[r].ci[l];
-  const double w2 = st[r].w2, p2 = w2 - c2;
-  const bool again = first && !(p2 > 0.01 * w2);
-  const double nrm = again ? 0.0 : sqrt(p2 > 0.0 ? p2 : 0.0);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (first) st[r].reorth = again;
-    if (!again) {
-      st[r].wnorm = nrm;
-      st[r].hr[j * (GM_MAXM + 1) + j + 1] = nrm;
-      st[r].hi[j * (GM_MAXM + 1) + j + 1] = 0.0;
-    }
+  if (first && blockIdx.x == 0 && threadIdx.x == 0) {
+    double c2 = 0.0;
+    for (int l = 0; l < NV; ++l) c2 += st[r].cr[l] * st[r].cr[l] + st[r].ci[l] * st[r].ci[l];
+    const double w2 = st[r].w2;
+    st[r].reorth = !(w2 - c2 > 0.01 * w2);
   }
   if (!valid) return;
   Spinor<double> ww;
@@ -193,14 +181,7 @@ __global__ __launch_bounds__(256) void gm_multiaxpy_kernel(Geom g, Field<S> V, s
 #pragma unroll
     for (int k = 0; k < 12; ++k) ww.v[k] = ww.v[k] - cmul(c, vv.v[k]);
   }
-  if (again) {
-    store_spinor(w, r, par, s, ww);
-    return;
-  }
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) ww.v[k] = inv * ww.v[k];
-  store_spinor(vnext, r, par, s, ww);
+  store_spinor(w, r, par, s, ww);
 }
 
 #define GM_NV_CASES(X)                                                                                              \
@@ -225,11 +206,11 @@ hipError_t launch_multidot(int nv, dim3 grid, dim3 blk, hipStream_t st, const Ge
 
 template <typename SV>
 hipError_t launch_multiaxpy(int nv, dim3 grid, dim3 blk, hipStream_t st, const Geom& g, Field<SV> V,
-                            size_t vstride, Field<SV> w, Field<SV> vnext, int n, GmState* S, int first, int j) {
+                            size_t vstride, Field<SV> w, int n, GmState* S, int first) {
   switch (nv) {
 #define GM_AXPY(N)                                                                                               \
   case N:                                                                                                        \
-    hipLaunchKernelGGL((gm_multiaxpy_kernel<N, SV>), grid, blk, 0, st, g, V, vstride, w, vnext, n, S, first, j); \
+    hipLaunchKernelGGL((gm_multiaxpy_kernel<N, SV>), grid, blk, 0, st, g, V, vstride, w, n, S, first);           \
     break;
     GM_NV_CASES(GM_AXPY)
 #undef GM_AXPY
@@ -533,8 +514,10 @@ int run_fgmres_t(mfq_handle* h, int n, const mfq_solve_params* P, hipStream_t st
         HIPCHK(launch_multidot<S>(j + 1, grid, blk, s, g, V, fch, W, n, part, first, Sg));
         hipLaunchKernelGGL(gm_dots_finish_kernel, dim3((n * (j + 2) + 3) / 4), dim3(256), 0, s, part, nblk, j + 1,
                            n, Sg, j, first);
-        HIPCHK(launch_multiaxpy<S>(j + 1, grid, blk, s, g, V, fch, W, vj(V, j + 1), n, Sg, first, j));
+        HIPCHK(launch_multiaxpy<S>(j + 1, grid, blk, s, g, V, fch, W, n, Sg, first));
       }
+      if ((rc = norm_finish(W, j, 0, s))) return rc;
+      hipLaunchKernelGGL((gm_scale_kernel<S, S>), grid, blk, 0, s, g, W, vj(V, j + 1), n, Sg);
       hipLaunchKernelGGL(gm_givens_kernel, dim3((n + 63) / 64), dim3(64), 0, s, Sg, n, j, m, tol2);
       HIPCHK(hipGetLastError());
     }

@@ -146,6 +146,27 @@ def test_fgmres_restart_lengths_meet_tolerance(restart, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("precond", ["identity", "ptc"])
+def test_fgmres_second_gram_schmidt_pass(precond, prec):
+    """kappa = 0.002: |kappa H| <= 16 kappa, so D^+D is within 0.07 of the
+    identity and A z_j lies within 7 % of the span of the basis; the first
+    projection removes more than 99 % of |w|^2 on every step and the second
+    pass (its sums reduced inside the update, which also closes the step with
+    the Givens rotations) runs each time.  The solution meets the tolerance
+    against the oracle's operator."""
+    dims, bc, kappa = (4, 4, 4, 8), "sf", 0.002
+    u = synth.random_links(dims, bc, 0.3, 1000)
+    lat = mfq.Lattice(dims, bc, kappa, to_dev(u))
+    lat.precond_init(seed=3, scale=0.02)
+    b = synth.gaussian_spinors(dims, bc, 3, 2040)
+    x, stats, rc = lat.solve(to_dev(b), tol=1e-10, precond=precond, prec=prec, max_iter=400)
+    note(f"fgmres second pass {precond} {prec}: rc {rc} iters {[s['iters'] for s in stats]}")
+    assert rc == 0 and all(s["status"] == 0 for s in stats), stats
+    _solve_check(lat, native.NativeWilson(dims, bc, kappa, u), b, x, 1e-10)
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("precond", ["identity", "ptc"])
 def test_fgmres_graph_replays_match_eager(precond, prec):
     """One restart cycle is captured as a graph and replayed for every cycle
     and by later solves on the same handle.  The reductions have a fixed
