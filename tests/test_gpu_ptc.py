@@ -150,8 +150,7 @@ def test_fgmres_second_gram_schmidt_pass(precond, prec):
     """kappa = 0.002: |kappa H| <= 16 kappa, so D^+D is within 0.07 of the
     identity and A z_j lies within 7 % of the span of the basis; the first
     projection removes more than 99 % of |w|^2 on every step and the second
-    pass (its sums reduced inside the update, which also closes the step with
-    the Givens rotations) runs each time.  The solution meets the tolerance
+    Gram-Schmidt pass runs each time.  The solution meets the tolerance
     against the oracle's operator."""
     dims, bc, kappa = (4, 4, 4, 8), "sf", 0.002
     u = synth.random_links(dims, bc, 0.3, 1000)
